@@ -1,0 +1,98 @@
+"""Pins of the oracle's V-cycle, setup and outer FGMRES (no GPU)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, coarse, mg
+from helpers import dense_from_apply, relerr
+
+L = (4, 4, 4, 4)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    """The 4^4 configuration: eps 0.3, m0 -0.1, c_sw 1, 2^4 blocks, Ntv 8,
+    3 setup iterations, SAP with 4 MR steps."""
+    U = synth.su3_field(L, 0.3, 101)
+    p = mg.Params(L, (2, 2, 2, 2), -0.1, 1.0, 8, n_setup=3)
+    M = mg.MG(p, U)
+    M.setup(synth.gaussian_spinors(L, 8, 102))
+    return M
+
+
+def test_setup_produces_orthonormal_basis(c1):
+    M = c1
+    shp = (L[3], L[2], L[1], L[0], 4, 3)
+    R = dense_from_apply(lambda y: coarse.restrict(M.blk, M.W, y), shp)
+    assert np.abs(R @ R.conj().T - np.eye(R.shape[0])).max() < 1e-13
+    # the final test vectors lie in the span of the prolongation
+    P = R.conj().T
+    for j in range(8):
+        v = M.V[j].reshape(-1)
+        assert relerr(P @ (R @ v), v) < 1e-12
+
+
+def test_vcycle_homogeneous(c1):
+    M = c1
+    y = synth.gaussian_spinors(L, 1, 141)[0]
+    a = M.vcycle(y)
+    b = M.vcycle((0.5 + 2j) * y)
+    assert relerr(b, (0.5 + 2j) * a) < 1e-12
+
+
+def test_vcycle_is_good_preconditioner(c1):
+    M = c1
+    y = synth.gaussian_spinors(L, 1, 142)[0]
+    x = M.vcycle(y)
+    r = y - M.D(x)
+    assert np.linalg.norm(r) < 0.2 * np.linalg.norm(y)
+
+
+def test_solve_reaches_tolerance_and_dense_solution(c1):
+    M = c1
+    f = synth.gaussian_spinors(L, 1, 103)[0]
+    u, st = M.solve(f, tol=1e-10)
+    assert mg.true_relres(M.D, u, f) <= 1e-10
+    shp = f.shape
+    D = dense_from_apply(M.D, shp)
+    ud = np.linalg.solve(D, f.reshape(-1))
+    kappa = np.linalg.cond(D)
+    assert relerr(u.reshape(-1), ud) <= kappa * 1e-10
+    assert st['iterations'] < 30
+
+
+def test_solve_zero_rhs(c1):
+    f = np.zeros((L[3], L[2], L[1], L[0], 4, 3), dtype=complex)
+    u, st = c1.solve(f)
+    assert np.all(u == 0) and st['relres'] == 0.0
+
+
+def test_fgmres_textbook_minimal_residual():
+    """With a fixed linear right preconditioner, FGMRES after k iterations
+    minimises ||b - A u|| over u in M^{-1} K_k(A M^{-1}, b)."""
+    rng = np.random.default_rng(3)
+    n = 50
+    A = np.eye(n) * 2 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    Minv = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    k = 6
+    u, st = mg.fgmres(lambda v: A @ v, lambda v: Minv @ v, b, None, 0.0, 20, 100, fixed_its=k)
+    AM = A @ Minv
+    K = np.array([np.linalg.matrix_power(AM, j) @ b for j in range(k)]).T
+    c, *_ = np.linalg.lstsq(AM @ K, b, rcond=None)
+    assert relerr(u, Minv @ K @ c) < 1e-10
+    # the Givens estimate at a normal stop equals the true residual
+    u2, st2 = mg.fgmres(lambda v: A @ v, lambda v: Minv @ v, b, None, 1e-12, 20, 200)
+    assert np.linalg.norm(b - A @ u2) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_solve_with_point_sources_and_restart():
+    """A point source and a short restart still reach 1e-10 (true residual)."""
+    U = synth.su3_field(L, 0.5, 301)
+    p = mg.Params(L, (2, 2, 2, 2), -0.2, 1.0, 8, n_setup=1, outer_restart=3)
+    M = mg.MG(p, U)
+    M.setup(synth.gaussian_spinors(L, 8, 302))
+    f = synth.point_sources(L)[7]
+    u, st = M.solve(f)
+    assert mg.true_relres(M.D, u, f) <= 1e-10
+    assert st['restarts'] >= 2

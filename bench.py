@@ -1,0 +1,248 @@
+"""Benchmark: time-to-solution of the two-level DD-alpha-AMG solve on one
+MI355X, mixed precision vs the plain FP64 path, plus the HBM roofline of the
+Wilson-clover dslash and the coarse stencil D_c.
+
+One step = the whole hot path on one batch: the adaptive setup (Alg. 4/5,
+24 test vectors) and the FGMRES(20) solve of the 12 point-source right-hand
+sides of the 32^3 x 64 workload (eps 0.5, m0 -0.2, c_sw 1, 4^4 blocks) to
+relative residual 1e-10, all inputs resident in HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c3|c2|c1]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: L (x, y, z, t), block, eps, m0, ntv, nrhs, rhs kind, seeds (gauge, tv)
+    "c3": dict(L=(32, 32, 32, 64), block=(4, 4, 4, 4), eps=0.5, m0=-0.2, ntv=24, nrhs=12, rhs="point",
+               seeds=(301, 302), name="32^3x64 eps0.5 m0-0.2 csw1 blocks4^4 Ntv24 12 point sources"),
+    "c2": dict(L=(16, 16, 16, 16), block=(4, 4, 4, 4), eps=0.5, m0=-0.2, ntv=20, nrhs=8, rhs="gauss",
+               seeds=(201, 202), name="16^4 eps0.5 m0-0.2 csw1 blocks4^4 Ntv20 8 gaussian rhs"),
+    "c1": dict(L=(4, 4, 4, 4), block=(2, 2, 2, 2), eps=0.3, m0=-0.1, ntv=8, nrhs=1, rhs="gauss",
+               seeds=(101, 102), name="4^4 eps0.3 m0-0.1 csw1 blocks2^4 Ntv8 1 gaussian rhs"),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(w):
+    import numpy as np
+    import synth
+    L = w["L"]
+    U = synth.su3_field(L, w["eps"], w["seeds"][0])
+    tv = synth.gaussian_spinors(L, w["ntv"], w["seeds"][1])
+    if w["rhs"] == "point":
+        f = synth.point_sources(L)[: w["nrhs"]]
+    else:
+        f = synth.gaussian_spinors(L, w["nrhs"], 203)
+    return U, np.ascontiguousarray(tv), np.ascontiguousarray(f)
+
+
+def run_path(dd, torch, w, prec, U_d, tv_d, f_d, steps, warmup):
+    p = dd.default_params(L=w["L"], block=w["block"], m0=w["m0"], csw=1.0, ntv=w["ntv"], prec=prec,
+                          max_rhs=max(w["nrhs"], 1), outer_restart=20)
+    ctx = dd.Context(p, U_d)
+    nrhs = w["nrhs"]
+    u = torch.zeros_like(f_d)
+    res = {"setup_ms": [], "solve_ms": [], "step_ms": []}
+    st = None
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.mg_setup(tv_d)
+        t1 = time.perf_counter()
+        u.zero_()
+        ctx.reset_stats()
+        rc, st = ctx.solve(u, f_d, nrhs, 1e-10)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rc != 0:
+            raise RuntimeError("solve did not converge: %s" % st)
+        if it >= warmup:
+            res["setup_ms"].append((t1 - t0) * 1e3)
+            res["solve_ms"].append((t2 - t1) * 1e3)
+            res["step_ms"].append((t2 - t0) * 1e3)
+        log("  prec %d step %d: setup %.1f ms solve %.1f ms outer its %d coarse its max %d" %
+            (prec, it, (t1 - t0) * 1e3, (t2 - t1) * 1e3, st["outer_iterations"], st["coarse_iterations_max"]))
+    res["stats"] = st
+    res["ctx"] = ctx
+    res["u"] = u
+    return res
+
+
+def time_kernel(torch, fn, reps):
+    """Average duration of one launch of fn (a single kernel on torch's
+    current stream) measured with HIP events around reps launches."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def kernel_rooflines(dd, torch, ctx, w, reps=50):
+    V = 1
+    for x in w["L"]:
+        V *= x
+    nb = ctx.nblocks
+    nc = 2 * w["ntv"]
+    out = {}
+    # dslash, FP16 links/clover + per-site FP32 scales, FP32 spinors, 1 rhs
+    a = torch.randn(12 * V * 2, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = time_kernel(torch, lambda: ctx.dirac_apply_internal(b, a, 1, dd.MIXED16), reps)
+    bytes_site = 96 + 96 + (36 * 4 + 4) + (72 * 2 + 4)
+    out["dslash_mixed16"] = dict(ms=ms, bytes=bytes_site * V, gbs=bytes_site * V / ms / 1e6)
+    a64 = torch.randn(12 * V * 2, dtype=torch.float64, device="cuda")
+    b64 = torch.empty_like(a64)
+    ms = time_kernel(torch, lambda: ctx.dirac_apply_internal(b64, a64, 1, dd.FP64), reps)
+    bytes_site = 192 + 192 + 576 + 576
+    out["dslash_fp64"] = dict(ms=ms, bytes=bytes_site * V, gbs=bytes_site * V / ms / 1e6)
+    # coarse stencil (FP16 D_c + per-(site, slot) scale, FP32 vectors)
+    for nr in (1, w["nrhs"]):
+        x = torch.randn(nr * nb * nc * 2, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        ms = time_kernel(torch, lambda: ctx.coarse_apply_internal(y, x, nr), reps)
+        by = nb * (9 * nc * nc * 4 + 9 * 4 + nr * 2 * nc * 8)
+        out["coarse_mixed16_%drhs" % nr] = dict(ms=ms, bytes=by, gbs=by / ms / 1e6)
+    return out
+
+
+def cpu_baseline(w):
+    """Time the oracle (numpy, one thread) on a bounded sample and scale it to
+    the workload: the full setup + one-rhs solve on the 8^4 lattice with the
+    same parameters (smallest lattice with an even number of 4^4 blocks per
+    direction), scaled by the volume ratio (setup) and by volume ratio x nrhs
+    (solve; the oracle solves right-hand sides one after another)."""
+    code = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+import numpy as np
+import synth
+from oracle import mg
+L = (8, 8, 8, 8)
+U = synth.su3_field(L, %r, 301)
+p = mg.Params(L, %r, %r, 1.0, %d)
+M = mg.MG(p, U)
+t0 = time.perf_counter()
+M.setup(synth.gaussian_spinors(L, %d, 302))
+t1 = time.perf_counter()
+f = synth.point_sources(L)[0]
+u, st = M.solve(f)
+t2 = time.perf_counter()
+print(json.dumps(dict(setup=t1 - t0, solve=t2 - t1, its=st["iterations"], relres=st["relres"])))
+""" % (ROOT, w["eps"], tuple(w["block"]), w["m0"], w["ntv"], w["ntv"])
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    t = time.perf_counter()
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if p.returncode != 0:
+        raise RuntimeError(p.stderr)
+    r = json.loads(p.stdout.strip().splitlines()[-1])
+    V = 1
+    for x in w["L"]:
+        V *= x
+    scale = V / 8 ** 4
+    est = r["setup"] * scale + r["solve"] * scale * w["nrhs"]
+    return dict(value=est, unit="s", cores=1, kind="oracle",
+                sample="oracle setup + 1-rhs solve on 8^4 (same eps/m0/csw/blocks/Ntv, %.1f s wall, %d outer its, "
+                       "relres %.1e), scaled x%d volume for setup and x%d volume x %d rhs for the solve"
+                       % (time.perf_counter() - t, r["its"], r["relres"], scale, scale, w["nrhs"]),
+                sample_setup_s=r["setup"], sample_solve_s=r["solve"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the lattice would be split "
+              "along t across GPUs with halo exchange; see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1512_04506_amd as dd
+    w = WORKLOADS[args.workload]
+    log("workload", w["name"])
+    t = time.perf_counter()
+    U, tv, f = make_inputs(w)
+    log("inputs generated in %.1f s" % (time.perf_counter() - t))
+    U_d = torch.from_numpy(U).cuda()
+    tv_d = torch.from_numpy(tv).cuda()
+    f_d = torch.from_numpy(f).cuda()
+    del U, tv
+    mixed = run_path(dd, torch, w, dd.MIXED16, U_d, tv_d, f_d, args.steps, args.warmup)
+    roof = kernel_rooflines(dd, torch, mixed["ctx"], w)
+    log("kernels:", json.dumps(roof))
+    st = mixed["stats"]
+    mixed["ctx"].close()
+    del mixed["ctx"], mixed["u"]
+    torch.cuda.empty_cache()
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_path(dd, torch, w, dd.FP64, U_d, tv_d, f_d, max(1, args.steps // 2), 0)
+        fp64["ctx"].close()
+        del fp64["ctx"], fp64["u"]
+        torch.cuda.empty_cache()
+    ms = sum(mixed["step_ms"]) / len(mixed["step_ms"])
+    dom = roof["dslash_mixed16"]
+    line = {
+        "metric": "time-to-solution (rel.res 1e-10) 32^3x64, mixed vs FP64; dslash/D_c HBM GB/s",
+        "value": ms / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (fp16 storage), f64 outer",
+        "data": "synthetic seeded SU(3) field and point sources",
+        "config": {"workload": w["name"], "nrhs": w["nrhs"], "outer": "FGMRES(20)", "tol": 1e-10},
+        "setup_ms": sum(mixed["setup_ms"]) / len(mixed["setup_ms"]),
+        "solve_ms": sum(mixed["solve_ms"]) / len(mixed["solve_ms"]),
+        "outer_iterations": st["outer_iterations"],
+        "coarse_iterations_max": st["coarse_iterations_max"],
+        "relres_max": max(st["relres"]),
+        "kernels": roof,
+        "roofline": {"bound": "hbm", "kernel": "dslash_mixed16", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None},
+    }
+    if fp64:
+        f64ms = sum(fp64["step_ms"]) / len(fp64["step_ms"])
+        line["fp64"] = {"ms_per_step": f64ms, "setup_ms": sum(fp64["setup_ms"]) / len(fp64["setup_ms"]),
+                        "solve_ms": sum(fp64["solve_ms"]) / len(fp64["solve_ms"]),
+                        "outer_iterations": fp64["stats"]["outer_iterations"]}
+        line["speedup_mixed_vs_fp64"] = f64ms / ms
+    if not args.no_cpu:
+        try:
+            line["cpu_baseline"] = cpu_baseline(w)
+        except Exception as e:  # the GPU figures stand on their own
+            line["cpu_baseline"] = {"error": str(e)[:200]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

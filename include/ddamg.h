@@ -1,0 +1,214 @@
+/*
+ * ddamg.h -- C ABI of the MI355X (gfx950) two-level DD-alpha-AMG library.
+ *
+ * Method: Heybrock, Rottmann, Georg, Wettig, "Adaptive algebraic multigrid
+ * on SIMD architectures", arXiv:1512.04506.  The library solves D u = f for
+ * the Wilson-clover operator D (Sec. 1) with flexible GMRES, right-
+ * preconditioned by the two-level V-cycle of Alg. 1: coarse-grid correction
+ * (Alg. 2: restriction R of Eq. R, even/odd coarse GMRES on D_c,
+ * prolongation P = R^dagger) followed by the domain-decomposition smoother of
+ * Alg. 3 (red/black multiplicative Schwarz with block-local MR).  R and D_c
+ * are built by the adaptive setup of Alg. 4 and Alg. 5.
+ *
+ * Conventions (fixed here because the paper leaves them open):
+ *   lattice L = (Lx, Ly, Lz, Lt), periodic in space, antiperiodic in time;
+ *   site index s = x + Lx (y + Ly (z + Lz t));
+ *   (D psi)(x) = A(x) psi(x) - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *                                          + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)],
+ *   A(x) = (4 + m0) + c_sw (i/4) sum_{mu,nu} sigma_{mu nu} F_{mu nu}(x) (clover
+ *   leaves), chiral gamma basis with g5 = diag(-1, -1, +1, +1): the
+ *   left-handed aggregate of a block holds spins {0, 1}, the right-handed one
+ *   spins {2, 3}.
+ *
+ * Canonical layouts at this boundary (all complex128 = interleaved re, im
+ * doubles, C order, DEVICE pointers on the context's device):
+ *   gauge field   [V][4 mu][3][3]                 (mu = x, y, z, t)
+ *   spinor fields [nrhs][V][4 spin][3 colour]
+ *   coarse fields [nrhs][Nblock][2 chirality][ntv] with block index
+ *                 bx + NBx (by + NBy (bz + NBz bt)), NB = L / block
+ *   coarse op     [Nblock][9 slot][2 ntv row][2 ntv col]; slot 0 = self,
+ *                 1 + 2 mu = forward neighbour, 2 + 2 mu = backward neighbour
+ *   test vectors  [ntv][V][4][3]
+ *   clover        [V][2 chirality][6][6]  (row/col = 3 spin_in_chirality + colour)
+ *
+ * Ownership: the caller owns every pointer it passes and keeps it valid for
+ * the duration of the call; the library never frees caller memory.  The
+ * library owns the context and its device workspace (hipMalloc at create).
+ *
+ * Streams: every call enqueues work on the context's stream.  dirac_apply,
+ * coarse_apply, mg_apply, mg_restrict, mg_prolong and the *_internal calls
+ * are asynchronous with respect to the host; mg_setup and solve synchronise
+ * (they test convergence) and return when done.  A context is not
+ * thread-safe; use one context per stream.
+ *
+ * Errors: 0 = OK, 1 = not converged (best iterate returned, stats filled);
+ * negative codes below.  Argument validation happens before any HIP call.
+ * No exception or abort crosses this boundary; ddamg_last_error() gives text.
+ */
+#ifndef DDAMG_H
+#define DDAMG_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDAMG_ABI_VERSION 1
+
+/* precision of the preconditioner (smoother, R/P, coarse solve) */
+#define DDAMG_FP64 0     /* everything FP64 */
+#define DDAMG_FP32 1     /* FP32 storage and arithmetic, FP64 outer FGMRES */
+#define DDAMG_MIXED16 2  /* FP16 storage of links, clover, test vectors and D_c
+                            with per-site / per-block FP32 scales, FP32
+                            arithmetic, FP64 outer FGMRES and setup Gram-Schmidt */
+
+#define DDAMG_OK 0
+#define DDAMG_NOT_CONVERGED 1
+#define DDAMG_EARG (-1)      /* invalid argument */
+#define DDAMG_ESTATE (-2)    /* call not valid in this state (e.g. before setup) */
+#define DDAMG_EHIP (-3)      /* HIP runtime error */
+#define DDAMG_ENOMEM (-4)    /* device allocation failed */
+#define DDAMG_ENUMERIC (-5)  /* NaN/Inf, singular coarse block, rank-deficient aggregate */
+
+typedef struct ddamg_ctx ddamg_ctx;
+
+typedef struct {
+  int32_t L[4];            /* lattice extents x, y, z, t */
+  int32_t block[4];        /* SAP block = aggregate extents; must divide L, and
+                              every L[mu]/block[mu] must be even (red/black SAP
+                              and coarse even/odd need it) */
+  double m0;               /* bare mass: diagonal 4 + m0 */
+  double csw;              /* clover coefficient */
+  int32_t ntv;             /* test vectors per aggregate (Sec. 2; 1 <= ntv <= 32,
+                              6 * block volume >= ntv) */
+  int32_t n_setup;         /* iterative setup passes after the initial 3 (Alg. 4) */
+  int32_t nu;              /* SAP cycles per smoother application (Alg. 3) */
+  int32_t n_mr;            /* MR steps per block solve */
+  double coarse_tol;       /* coarse solve stops at ||r_c|| <= tol ||y_c|| (Alg. 2) */
+  int32_t coarse_restart;  /* coarse GMRES restart length (<= 64) */
+  int32_t coarse_maxit;    /* coarse iteration cap per solve */
+  int32_t coarse_fixed_its;/* > 0: run exactly this many coarse iterations
+                              (deterministic mode, no tolerance test) */
+  int32_t outer_restart;   /* outer FGMRES restart length (<= 64) */
+  int32_t outer_maxit;     /* outer iteration cap */
+  int32_t prec;            /* DDAMG_FP64, DDAMG_FP32 or DDAMG_MIXED16 */
+  int32_t max_rhs;         /* largest nrhs of any later call (>= 1, <= 64) */
+} ddamg_params;
+
+typedef struct {
+  int32_t outer_iterations;     /* FGMRES iterations of the last solve */
+  int32_t outer_restarts;       /* restart cycles of the last solve */
+  int32_t coarse_solves;        /* coarse solves since the last reset */
+  int32_t coarse_iterations_max;/* largest iteration count of one coarse solve */
+  int64_t coarse_iterations;    /* total coarse iterations since the last reset */
+  int32_t nrhs;                 /* right-hand sides of the last solve */
+  int32_t converged;            /* 1 if every right-hand side converged */
+  double relres[64];            /* final FP64 true relative residual per rhs */
+  double setup_ms;              /* wall time of the last mg_setup */
+  double solve_ms;              /* wall time of the last solve */
+} ddamg_stats;
+
+/* Fills *p with the defaults: block 4^4, m0 = 0, csw = 1, ntv = 24,
+ * n_setup = 3, nu = 3, n_mr = 4, coarse_tol = 0.05, coarse_restart = 30,
+ * coarse_maxit = 300, coarse_fixed_its = 0, outer_restart = 20,
+ * outer_maxit = 2000, prec = DDAMG_MIXED16, max_rhs = 12. */
+void ddamg_default_params(ddamg_params* p);
+
+/* Checks p without touching the GPU.  Returns 0 or DDAMG_EARG and, if msg is
+ * not NULL, writes a NUL-terminated reason into msg[0..msg_len-1]. */
+int ddamg_validate_params(const ddamg_params* p, char* msg, size_t msg_len);
+
+/* Creates a context on the current HIP device.  gauge: canonical links
+ * (device, complex128), copied; the clover term A(x) is built from them
+ * (Alg. 7 names its blocks C^{hh}(x)) and all storage precisions are
+ * derived.  stream: hipStream_t the context enqueues on (NULL = default
+ * stream).  *out receives the context, or NULL on error. */
+int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg_ctx** out);
+
+int ddamg_destroy(ddamg_ctx* ctx);
+
+/* Text of the last error on ctx (or of the last failed create if ctx is NULL). */
+const char* ddamg_last_error(const ddamg_ctx* ctx);
+
+/* Adaptive setup, Alg. 4 with Alg. 5: tv_init (device, canonical test
+ * vectors [ntv][V][4][3]) are the random starting vectors; they are
+ * smoothed with N_smoother = 1, 2, 3 from a zero guess, R and D_c are
+ * built (aggregate Gram-Schmidt in FP64, D_c = R D P with backward couplings
+ * from Eq. dagger), the vectors are normalised, then n_setup passes apply
+ * the V-cycle to every test vector and rebuild R and D_c.  Synchronous. */
+int mg_setup(ddamg_ctx* ctx, const double* tv_init);
+
+/* Replaces the aggregate basis by W (device, canonical [ntv][V][4][3],
+ * orthonormal on every aggregate, e.g. as returned by ddamg_export_basis)
+ * and rebuilds D_c = R D P from it (Alg. 5 without the Gram-Schmidt).
+ * Synchronous. */
+int ddamg_import_basis(ddamg_ctx* ctx, const double* W);
+
+/* Exports the aggregate basis (the rows of R, i.e. the columns of P = R^dag,
+ * as fields), dequantised to FP64, canonical [ntv][V][4][3]. */
+int ddamg_export_basis(ddamg_ctx* ctx, double* W);
+
+/* Exports the setup's current test vectors (FP64, canonical [ntv][V][4][3]). */
+int ddamg_export_tv(ddamg_ctx* ctx, double* tv);
+
+/* Exports D_c (Eq. cgo), dequantised, as [Nblock][9][2ntv][2ntv] complex128. */
+int ddamg_export_coarse(ddamg_ctx* ctx, double* Dc);
+
+/* Exports the clover term A(x) in FP64 as [V][2][6][6] complex128. */
+int ddamg_export_clover(ddamg_ctx* ctx, double* A);
+
+/* One V-cycle (Alg. 1) on nrhs canonical spinor fields: x = M^{-1} y.
+ * Runs in the context's precision; x, y complex128 [nrhs][V][4][3],
+ * x != y.  Requires setup. */
+int mg_apply(ddamg_ctx* ctx, double* x, const double* y, int nrhs);
+
+/* out = D in (Sec. 1) for nrhs canonical spinor fields with the links and
+ * clover stored in precision prec (DDAMG_FP64 / FP32 / MIXED16); the result
+ * is returned in FP64.  out != in. */
+int dirac_apply(ddamg_ctx* ctx, double* out, const double* in, int nrhs, int prec);
+
+/* out = D_c in on canonical coarse fields [nrhs][Nblock][2][ntv], using the
+ * stored (possibly FP16) D_c with the context's arithmetic.  Requires setup. */
+int coarse_apply(ddamg_ctx* ctx, double* out, const double* in, int nrhs);
+
+/* y_c = R y (Eq. R) and x = P x_c (P = R^dag, Alg. 2) on canonical fields. */
+int mg_restrict(ddamg_ctx* ctx, double* yc, const double* y, int nrhs);
+int mg_prolong(ddamg_ctx* ctx, double* x, const double* xc, int nrhs);
+
+/* Solves D u = f for nrhs right-hand sides with FGMRES(outer_restart),
+ * right-preconditioned by the V-cycle (Sec. 1), to ||f - D u|| <= tol ||f||
+ * per rhs, the residual recomputed in FP64.  u holds the initial guess on
+ * entry (zero recommended) and the solution on return.  u, f canonical,
+ * u != f.  st may be NULL.  Returns 0, DDAMG_NOT_CONVERGED or an error.
+ * Synchronous. */
+int solve(ddamg_ctx* ctx, double* u, const double* f, int nrhs, double tol, ddamg_stats* st);
+
+/* Fills *st with the counters of the last calls; ddamg_reset_stats zeroes
+ * the coarse-solve counters. */
+int ddamg_get_stats(const ddamg_ctx* ctx, ddamg_stats* st);
+int ddamg_reset_stats(ddamg_ctx* ctx);
+
+/* ---- internal-layout fast path (benchmarks) --------------------------
+ * Spinor fields in the library's internal layout: site-major
+ * structure-of-arrays complex, element (rhs, comp, site) at
+ * (rhs * 12 + comp) * V + site, comp = 3 spin + colour, complex128 for
+ * DDAMG_FP64 and complex64 for DDAMG_FP32 / DDAMG_MIXED16.  No layout
+ * conversion is performed; out != in; asynchronous. */
+int dirac_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
+
+/* Coarse fields in the internal layout of the context's arithmetic
+ * (complex128 for DDAMG_FP64, complex64 otherwise): [nrhs][Nblock][2 ntv]
+ * with coarse sites in the internal order (even coarse sites first). */
+int coarse_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs);
+
+/* Geometry queries: number of sites, blocks, and sizes in bytes of one
+ * internal fine / coarse field of one rhs for a precision. */
+int64_t ddamg_volume(const ddamg_ctx* ctx);
+int32_t ddamg_nblocks(const ddamg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

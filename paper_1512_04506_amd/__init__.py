@@ -1,0 +1,249 @@
+"""Python binding of libddamg.so, the gfx950 two-level DD-alpha-AMG library.
+
+Thin ctypes marshalling only: every step of the method runs in the HIP
+kernels behind the C ABI declared in include/ddamg.h.  The functions keep the
+ABI's names (mg_setup, mg_apply, dirac_apply, coarse_apply, solve, ...).
+PyTorch provides device memory and the stream: arguments are complex128
+CUDA/HIP tensors in the canonical layouts of the header, for example spinor
+fields of shape (nrhs, Lt, Lz, Ly, Lx, 4, 3).
+
+Importing this package fails loudly when the library is not built; there is
+no CPU fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddamg.so")
+
+FP64, FP32, MIXED16 = 0, 1, 2
+OK, NOT_CONVERGED = 0, 1
+ERRORS = {-1: "invalid argument", -2: "wrong state", -3: "HIP error", -4: "out of memory", -5: "numerical failure"}
+
+EXPORTS = (
+    "ddamg_default_params", "ddamg_validate_params", "ddamg_create", "ddamg_destroy", "ddamg_last_error",
+    "mg_setup", "ddamg_import_basis", "ddamg_export_basis", "ddamg_export_tv", "ddamg_export_coarse",
+    "ddamg_export_clover", "mg_apply", "dirac_apply", "coarse_apply", "mg_restrict", "mg_prolong", "solve",
+    "ddamg_get_stats", "ddamg_reset_stats", "dirac_apply_internal", "coarse_apply_internal", "ddamg_volume",
+    "ddamg_nblocks",
+)
+
+
+class DDAMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("ddamg error %d (%s): %s" % (code, ERRORS.get(code, "?"), msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32 * 4), ("block", ctypes.c_int32 * 4), ("m0", ctypes.c_double),
+        ("csw", ctypes.c_double), ("ntv", ctypes.c_int32), ("n_setup", ctypes.c_int32),
+        ("nu", ctypes.c_int32), ("n_mr", ctypes.c_int32), ("coarse_tol", ctypes.c_double),
+        ("coarse_restart", ctypes.c_int32), ("coarse_maxit", ctypes.c_int32),
+        ("coarse_fixed_its", ctypes.c_int32), ("outer_restart", ctypes.c_int32),
+        ("outer_maxit", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("outer_iterations", ctypes.c_int32), ("outer_restarts", ctypes.c_int32),
+        ("coarse_solves", ctypes.c_int32), ("coarse_iterations_max", ctypes.c_int32),
+        ("coarse_iterations", ctypes.c_int64), ("nrhs", ctypes.c_int32), ("converged", ctypes.c_int32),
+        ("relres", ctypes.c_double * 64), ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "relres"}
+        d["relres"] = list(self.relres[: max(self.nrhs, 0)])
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libddamg.so is not built (run paper_1512_04506_amd/build.py); "
+                          "there is no fallback implementation")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp, i32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int
+    sig = {
+        "ddamg_default_params": (None, [ctypes.POINTER(Params)]),
+        "ddamg_validate_params": (i32, [ctypes.POINTER(Params), ctypes.c_char_p, ctypes.c_size_t]),
+        "ddamg_create": (i32, [ctypes.POINTER(Params), dp, vp, ctypes.POINTER(vp)]),
+        "ddamg_destroy": (i32, [vp]),
+        "ddamg_last_error": (ctypes.c_char_p, [vp]),
+        "mg_setup": (i32, [vp, dp]),
+        "ddamg_import_basis": (i32, [vp, dp]),
+        "ddamg_export_basis": (i32, [vp, dp]),
+        "ddamg_export_tv": (i32, [vp, dp]),
+        "ddamg_export_coarse": (i32, [vp, dp]),
+        "ddamg_export_clover": (i32, [vp, dp]),
+        "mg_apply": (i32, [vp, dp, dp, i32]),
+        "dirac_apply": (i32, [vp, dp, dp, i32, i32]),
+        "coarse_apply": (i32, [vp, dp, dp, i32]),
+        "mg_restrict": (i32, [vp, dp, dp, i32]),
+        "mg_prolong": (i32, [vp, dp, dp, i32]),
+        "solve": (i32, [vp, dp, dp, i32, ctypes.c_double, ctypes.POINTER(Stats)]),
+        "ddamg_get_stats": (i32, [vp, ctypes.POINTER(Stats)]),
+        "ddamg_reset_stats": (i32, [vp]),
+        "dirac_apply_internal": (i32, [vp, vp, vp, i32, i32]),
+        "coarse_apply_internal": (i32, [vp, vp, vp, i32]),
+        "ddamg_volume": (ctypes.c_int64, [vp]),
+        "ddamg_nblocks": (ctypes.c_int32, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def default_params(**kw):
+    """ddamg_default_params, then keyword overrides (L and block as 4-tuples
+    in x, y, z, t order)."""
+    p = Params()
+    lib.ddamg_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k in ("L", "block"):
+            arr = getattr(p, k)
+            for i in range(4):
+                arr[i] = int(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def validate_params(p):
+    """(code, message) of ddamg_validate_params; touches no GPU."""
+    buf = ctypes.create_string_buffer(256)
+    rc = lib.ddamg_validate_params(ctypes.byref(p), buf, 256)
+    return rc, buf.value.decode()
+
+
+def _ptr(t, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() * t.element_size() != numel:
+        raise ValueError("%s has %d bytes, expected %d" % (name, t.numel() * t.element_size(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One ddamg_ctx on the current device and torch's current stream."""
+
+    def __init__(self, params, gauge, stream=None):
+        import torch
+        self.params = params
+        self.L = tuple(params.L)
+        self.V = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self.nblocks = 1
+        for m in range(4):
+            self.nblocks *= self.L[m] // params.block[m]
+        self.ntv = params.ntv
+        if gauge.dtype != torch.complex128:
+            raise TypeError("gauge must be complex128")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib.ddamg_create(ctypes.byref(params), _ptr(gauge, "gauge", self.V * 36 * 16),
+                              ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise DDAMGError(rc, lib.ddamg_last_error(None).decode())
+        self.h = h
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc):
+        if rc < 0:
+            raise DDAMGError(rc, lib.ddamg_last_error(self.h).decode())
+        return rc
+
+    def fine_bytes(self, nrhs):
+        return nrhs * self.V * 12 * 16
+
+    def coarse_bytes(self, nrhs):
+        return nrhs * self.nblocks * 2 * self.ntv * 16
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ddamg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI -----------------------------------------------------------
+    def mg_setup(self, tv_init):
+        return self._check(lib.mg_setup(self.h, _ptr(tv_init, "tv_init", self.fine_bytes(self.ntv))))
+
+    def import_basis(self, W):
+        return self._check(lib.ddamg_import_basis(self.h, _ptr(W, "W", self.fine_bytes(self.ntv))))
+
+    def export_basis(self, W):
+        return self._check(lib.ddamg_export_basis(self.h, _ptr(W, "W", self.fine_bytes(self.ntv))))
+
+    def export_tv(self, tv):
+        return self._check(lib.ddamg_export_tv(self.h, _ptr(tv, "tv", self.fine_bytes(self.ntv))))
+
+    def export_coarse(self, Dc):
+        n = self.nblocks * 9 * (2 * self.ntv) ** 2 * 16
+        return self._check(lib.ddamg_export_coarse(self.h, _ptr(Dc, "Dc", n)))
+
+    def export_clover(self, A):
+        return self._check(lib.ddamg_export_clover(self.h, _ptr(A, "A", self.V * 72 * 16)))
+
+    def mg_apply(self, x, y, nrhs):
+        b = self.fine_bytes(nrhs)
+        return self._check(lib.mg_apply(self.h, _ptr(x, "x", b), _ptr(y, "y", b), nrhs))
+
+    def dirac_apply(self, out, inp, nrhs, prec=FP64):
+        b = self.fine_bytes(nrhs)
+        return self._check(lib.dirac_apply(self.h, _ptr(out, "out", b), _ptr(inp, "in", b), nrhs, prec))
+
+    def dirac_apply_internal(self, out, inp, nrhs, prec):
+        es = 16 if prec == FP64 else 8
+        b = nrhs * self.V * 12 * es
+        return self._check(lib.dirac_apply_internal(self.h, _ptr(out, "out", b), _ptr(inp, "in", b), nrhs, prec))
+
+    def coarse_apply(self, out, inp, nrhs):
+        b = self.coarse_bytes(nrhs)
+        return self._check(lib.coarse_apply(self.h, _ptr(out, "out", b), _ptr(inp, "in", b), nrhs))
+
+    def coarse_apply_internal(self, out, inp, nrhs):
+        es = 16 if self.params.prec == FP64 else 8
+        b = nrhs * self.nblocks * 2 * self.ntv * es
+        return self._check(lib.coarse_apply_internal(self.h, _ptr(out, "out", b), _ptr(inp, "in", b), nrhs))
+
+    def mg_restrict(self, yc, y, nrhs):
+        return self._check(lib.mg_restrict(self.h, _ptr(yc, "yc", self.coarse_bytes(nrhs)),
+                                           _ptr(y, "y", self.fine_bytes(nrhs)), nrhs))
+
+    def mg_prolong(self, x, xc, nrhs):
+        return self._check(lib.mg_prolong(self.h, _ptr(x, "x", self.fine_bytes(nrhs)),
+                                          _ptr(xc, "xc", self.coarse_bytes(nrhs)), nrhs))
+
+    def solve(self, u, f, nrhs, tol=1e-10):
+        """Returns (code, stats dict); code 0 = converged, 1 = not converged."""
+        st = Stats()
+        b = self.fine_bytes(nrhs)
+        rc = self._check(lib.solve(self.h, _ptr(u, "u", b), _ptr(f, "f", b), nrhs, tol, ctypes.byref(st)))
+        return rc, st.as_dict()
+
+    def stats(self):
+        st = Stats()
+        self._check(lib.ddamg_get_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        return self._check(lib.ddamg_reset_stats(self.h))

@@ -1,0 +1,1155 @@
+// C ABI of the library (include/ddamg.h) and the host-side orchestration of
+// the two-level method: adaptive setup (Alg. 4, Alg. 5), V-cycle (Alg. 1),
+// coarse-grid correction with the even/odd preconditioned coarse GMRES
+// (Alg. 2), SAP smoother (Alg. 3) and the FP64 outer flexible GMRES
+// (Sec. 1).  All arithmetic runs in the kernels of this library on the
+// context's stream; the host only sequences launches and reads back the
+// per-rhs convergence flags of the Krylov solvers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ddamg.h"
+#include "ddamg_internal.h"
+
+using namespace ddamg;
+
+namespace {
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCK(call)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw Fail{DDAMG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+
+inline void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Fail{DDAMG_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename X>
+X* dalloc(size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(X));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{DDAMG_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(X)) + " bytes failed"};
+  }
+  return static_cast<X*>(p);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename X>
+  X* get() const {
+    return static_cast<X*>(p);
+  }
+  template <typename X>
+  X* alloc(size_t n) {
+    release();
+    p = dalloc<X>(n);
+    return get<X>();
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct SolverBase;
+
+struct ddamg_ctx {
+  ddamg_params p{};
+  Geom g{};
+  hipStream_t st = nullptr;
+  std::string err;
+  // FP64 master fields and the derived storage precisions
+  DevBuf U64, A64, U32, A32, Uh, Uhs, Ah, Ahs;
+  // tables
+  DevBuf colour_blocks, b2i, i2b, nbr;
+  DevBuf status;
+  int* h_flags = nullptr;        // pinned host mirrors of small device arrays
+  double* h_dbl = nullptr;       // [128]
+  cx<double>* h_cx = nullptr;    // [64]
+  // canonical <-> internal staging
+  DevBuf stage_in, stage_out;
+  size_t stage_rhs = 0;
+  std::unique_ptr<SolverBase> sol;
+  bool setup_done = false;
+  ddamg_stats stats{};
+
+  GaugeView<double> gv64() const { return {U64.get<cx<double>>(), nullptr, A64.get<double>(), nullptr}; }
+  GaugeView<float> gv32() const { return {U32.get<cx<float>>(), nullptr, A32.get<float>(), nullptr}; }
+  GaugeView<__half> gvh() const {
+    return {Uh.get<__half2>(), Uhs.get<float>(), Ah.get<__half>(), Ahs.get<float>()};
+  }
+  void ensure_stage(int nrhs) {
+    if ((size_t)nrhs <= stage_rhs) return;
+    size_t n = (size_t)nrhs * 12 * g.V;
+    stage_in.alloc<cx<double>>(n);
+    stage_out.alloc<cx<double>>(n);
+    stage_rhs = nrhs;
+  }
+  void sync() { HIPCK(hipStreamSynchronize(st)); }
+  void free_pinned() {
+    if (h_flags) (void)hipHostFree(h_flags);
+    if (h_dbl) (void)hipHostFree(h_dbl);
+    if (h_cx) (void)hipHostFree(h_cx);
+    h_flags = nullptr;
+    h_dbl = nullptr;
+    h_cx = nullptr;
+  }
+};
+
+struct SolverBase {
+  virtual ~SolverBase() = default;
+  virtual void setup(const double* tv) = 0;
+  virtual void import_basis(const double* W) = 0;
+  virtual void export_basis(double* W) = 0;
+  virtual void export_tv(double* tv) = 0;
+  virtual void export_coarse(double* Dc) = 0;
+  virtual void vcycle_canon(double* x, const double* y, int nrhs) = 0;
+  virtual void coarse_canon(double* out, const double* in, int nrhs) = 0;
+  virtual void coarse_internal(void* out, const void* in, int nrhs) = 0;
+  virtual void restrict_canon(double* yc, const double* y, int nrhs) = 0;
+  virtual void prolong_canon(double* x, const double* xc, int nrhs) = 0;
+  virtual int solve(double* u, const double* f, int nrhs, double tol) = 0;
+  virtual void coarse_stats(int& calls, int64_t& its, int& itmax) const = 0;
+  virtual void reset_coarse_stats() = 0;
+};
+
+namespace {
+
+// Krylov workspace of one GMRES instance (coarse or outer)
+struct Krylov {
+  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, kdone, h1, h2, n2, part;
+  int m = 0, maxr = 0, ldh = 0;
+  ArnoldiState st{};
+  void alloc(int m_, int maxr_, size_t n_per_rhs) {
+    m = m_;
+    maxr = maxr_;
+    ldh = m + 1;
+    H.alloc<cx<double>>((size_t)maxr * (m + 1) * m);
+    cs.alloc<cx<double>>((size_t)maxr * m);
+    sn.alloc<cx<double>>((size_t)maxr * m);
+    g.alloc<cx<double>>((size_t)maxr * (m + 1));
+    y.alloc<cx<double>>((size_t)maxr * m);
+    est.alloc<double>(maxr);
+    inv_h.alloc<double>(maxr);
+    abstol.alloc<double>(maxr);
+    active.alloc<int>(maxr);
+    kdone.alloc<int>(maxr);
+    h1.alloc<cx<double>>((size_t)maxr * ldh);
+    h2.alloc<cx<double>>((size_t)maxr * ldh);
+    n2.alloc<cx<double>>(maxr);
+    part.alloc<cx<double>>((size_t)maxr * (m + 1) * blas_nchunks(n_per_rhs));
+    st.H = H.get<cx<double>>();
+    st.cs = cs.get<cx<double>>();
+    st.sn = sn.get<cx<double>>();
+    st.g = g.get<cx<double>>();
+    st.y = y.get<cx<double>>();
+    st.est = est.get<double>();
+    st.inv_h = inv_h.get<double>();
+    st.abstol = abstol.get<double>();
+    st.active = active.get<int>();
+    st.kdone = kdone.get<int>();
+    st.m = m;
+  }
+};
+
+template <typename T, typename S>
+struct Solver final : SolverBase {
+  ddamg_ctx* c;
+  Geom g;
+  hipStream_t st;
+  GaugeView<S> gv;   // smoother links/clover (storage S)
+  GaugeView<T> gva;  // links/clover used to assemble D_c (T)
+  int maxr;          // max(max_rhs, ntv)
+  // aggregate basis and coarse operator
+  DevBuf Wq, Wsc, Dq, Dsc, Dinv, tv;
+  // fine work vectors (T): y, x, r [maxr][12][V]
+  DevBuf fy, fx;
+  // coarse work vectors (T)
+  DevBuf yc, xc, te, ue, bo, cw, cV;
+  Krylov ck;
+  // outer FGMRES
+  DevBuf oV, oZ, ow, of, ou, oyT;
+  Krylov ok;
+  int outer_m = 0, outer_r = 0;
+  int coarse_calls = 0;
+  int64_t coarse_its_total = 0;
+  int coarse_its_max = 0;
+
+  void coarse_stats(int& calls, int64_t& its, int& itmax) const override {
+    calls = coarse_calls;
+    its = coarse_its_total;
+    itmax = coarse_its_max;
+  }
+  void reset_coarse_stats() override {
+    coarse_calls = 0;
+    coarse_its_total = 0;
+    coarse_its_max = 0;
+  }
+
+  size_t fsz() const { return (size_t)12 * g.V; }             // fine elements per rhs
+  size_t csz() const { return (size_t)g.nblocks * g.nc; }      // coarse elements per rhs
+  int nodd() const { return g.nblocks - g.neven; }
+  size_t osz() const { return (size_t)nodd() * g.nc; }
+  size_t esz() const { return (size_t)g.neven * g.nc; }
+
+  BasisView<S> bv() const { return {Wq.get<stc_t<S>>(), Wsc.get<float>()}; }
+  CoarseView<S> cv() const { return {Dq.get<stc_t<S>>(), Dsc.get<float>(), c->nbr.get<int>()}; }
+
+  Solver(ddamg_ctx* ctx, GaugeView<S> gvs, GaugeView<T> gvt) : c(ctx), g(ctx->g), st(ctx->st), gv(gvs), gva(gvt) {
+    maxr = std::max(c->p.max_rhs, g.ntv);
+    Wq.alloc<stc_t<S>>((size_t)g.ntv * fsz());
+    if (is_half<S>()) Wsc.alloc<float>((size_t)g.ntv * g.V);
+    Dq.alloc<stc_t<S>>((size_t)g.nblocks * 9 * g.nc * g.nc);
+    if (is_half<S>()) Dsc.alloc<float>((size_t)g.nblocks * 9);
+    Dinv.alloc<cx<T>>((size_t)g.neven * g.nc * g.nc);
+    tv.alloc<cx<T>>((size_t)g.ntv * fsz());
+    fy.alloc<cx<T>>((size_t)maxr * fsz());
+    fx.alloc<cx<T>>((size_t)maxr * fsz());
+    yc.alloc<cx<T>>((size_t)maxr * csz());
+    xc.alloc<cx<T>>((size_t)maxr * csz());
+    te.alloc<cx<T>>((size_t)maxr * esz());
+    ue.alloc<cx<T>>((size_t)maxr * esz());
+    bo.alloc<cx<T>>((size_t)maxr * osz());
+    cw.alloc<cx<T>>((size_t)maxr * osz());
+    const int mc = c->p.coarse_restart;
+    cV.alloc<cx<T>>((size_t)(mc + 1) * maxr * osz());
+    ck.alloc(mc, maxr, std::max(osz(), csz()));
+  }
+
+  // ------------------------------------------------------------ smoother
+  // nu cycles of red/black SAP on (x, y), Alg. 3
+  void sap(cx<T>* x, const cx<T>* y, int nrhs, int nu) {
+    for (int n = 0; n < nu; ++n)
+      for (int col = 0; col < 2; ++col)
+        launch_sap_phase<T, S>(x, y, gv, g, c->colour_blocks.get<int>(), col, c->p.n_mr, nrhs, st);
+  }
+
+  // -------------------------------------------------------- coarse solve
+  // S v = D_oo v - D_oe D_ee^{-1} D_eo v on odd compact vectors
+  // (v and w: odd-site vectors with rhs strides vstr and wstr)
+  void schur(cx<T>* w, size_t wstr, const cx<T>* v, size_t vstr, int nrhs) {
+    const CoarseView<S> C = cv();
+    launch_coarse_stencil<T, S>(te.get<cx<T>>(), esz(), 0, g.neven, nullptr, 0, nullptr, 0, 0, (T)0, v, vstr, g.neven,
+                                (T)1, C, g, nrhs, st);
+    launch_block_matvec<T>(ue.get<cx<T>>(), esz(), Dinv.get<cx<T>>(), te.get<cx<T>>(), esz(), g.neven, g.nc, nrhs, st);
+    launch_coarse_stencil<T, S>(w, wstr, g.neven, nodd(), nullptr, 0, v, vstr, g.neven, (T)1, ue.get<cx<T>>(), esz(),
+                                0, (T)-1, C, g, nrhs, st);
+  }
+
+  int read_any_active(const Krylov& k, int nrhs) {
+    HIPCK(hipMemcpyAsync(c->h_flags, k.active.get<int>(), sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    c->sync();
+    int any = 0;
+    for (int r = 0; r < nrhs; ++r) any |= c->h_flags[r];
+    return any;
+  }
+
+  // classical Gram-Schmidt twice against V_0..V_k, then |w|^2
+  template <typename Tv>
+  void cgs2(Krylov& K, Tv* Vb, size_t vsj, size_t vsr, int k, Tv* w, size_t wsr, size_t n, int nrhs) {
+    using E = typename std::remove_cv<decltype(Vb->r)>::type;
+    const int* act = K.active.get<int>();
+    launch_mdot<E>(K.h1.get<cx<double>>(), K.ldh, K.part.get<cx<double>>(), Vb, vsj, vsr, k + 1, w, wsr, n, nrhs, act,
+                   st);
+    launch_maxpy<E, E>(w, wsr, Vb, vsj, vsr, k + 1, K.h1.get<cx<double>>(), K.ldh, -1.0, n, nrhs, act, st);
+    launch_mdot<E>(K.h2.get<cx<double>>(), K.ldh, K.part.get<cx<double>>(), Vb, vsj, vsr, k + 1, w, wsr, n, nrhs, act,
+                   st);
+    launch_maxpy<E, E>(w, wsr, Vb, vsj, vsr, k + 1, K.h2.get<cx<double>>(), K.ldh, -1.0, n, nrhs, act, st);
+    launch_mdot<E>(K.n2.get<cx<double>>(), 1, K.part.get<cx<double>>(), w, 0, wsr, 1, w, wsr, n, nrhs, act, st);
+  }
+
+  // x_c = D_c^{-1} y_c approximately (Alg. 2), y_c/x_c full [nrhs][Nb][nc]
+  int coarse_solve(cx<T>* xcv, const cx<T>* ycv, int nrhs) {
+    const CoarseView<S> C = cv();
+    const size_t cs_ = csz();
+    const int fixed = c->p.coarse_fixed_its;
+    const int m = c->p.coarse_restart;
+    const int maxit = fixed > 0 ? fixed : c->p.coarse_maxit;
+    // ||y_c|| per rhs -> absolute tolerance (computed on the device)
+    launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), ycv, 0, cs_, 1, ycv, cs_, cs_, nrhs, nullptr,
+                   st);
+    launch_set_abstol(ck.abstol.get<double>(), ck.n2.get<cx<double>>(), fixed > 0 ? -1.0 : c->p.coarse_tol, nrhs, st);
+    // b_o = y_o - D_oe D_ee^{-1} y_e
+    launch_block_matvec<T>(te.get<cx<T>>(), esz(), Dinv.get<cx<T>>(), ycv, cs_, g.neven, g.nc, nrhs, st);
+    launch_coarse_stencil<T, S>(bo.get<cx<T>>(), osz(), g.neven, nodd(), ycv + esz(), cs_, nullptr, 0, 0, (T)0,
+                                te.get<cx<T>>(), esz(), 0, (T)-1, C, g, nrhs, st);
+    cx<T>* xo = xcv + esz();
+    HIPCK(hipMemsetAsync(xcv, 0, sizeof(cx<T>) * cs_ * nrhs, st));
+    cx<T>* Vb = cV.get<cx<T>>();
+    const size_t vsr = osz(), vsj = (size_t)maxr * osz();
+    int its = 0;
+    bool first = true;
+    while (its < maxit) {
+      // r = b_o - S x_o into V_0
+      if (first) {
+        launch_copy<T, T>(Vb, vsr, bo.get<cx<T>>(), osz(), osz(), nrhs, st);
+      } else {
+        schur(cw.get<cx<T>>(), osz(), xo, cs_, nrhs);
+        launch_sub<T>(Vb, vsr, bo.get<cx<T>>(), osz(), cw.get<cx<T>>(), osz(), osz(), nrhs, st);
+      }
+      first = false;
+      launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), Vb, 0, vsr, 1, Vb, vsr, osz(), nrhs,
+                     nullptr, st);
+      launch_arnoldi_start(ck.st, ck.n2.get<cx<double>>(), 1, nrhs, st);
+      launch_scale<T, T>(Vb, vsr, Vb, vsr, ck.inv_h.get<double>(), osz(), nrhs, nullptr, st);
+      if (!read_any_active(ck, nrhs)) break;
+      int k = 0;
+      for (; k < m && its < maxit; ++k) {
+        cx<T>* w = Vb + (size_t)(k + 1) * vsj;
+        schur(w, vsr, Vb + (size_t)k * vsj, vsr, nrhs);
+        cgs2(ck, Vb, vsj, vsr, k, w, vsr, osz(), nrhs);
+        launch_arnoldi_column(ck.st, k, ck.h1.get<cx<double>>(), ck.h2.get<cx<double>>(), ck.ldh,
+                              ck.n2.get<cx<double>>(), 1, nrhs, st);
+        launch_scale<T, T>(w, vsr, w, vsr, ck.inv_h.get<double>(), osz(), nrhs, nullptr, st);
+        ++its;
+        if (!read_any_active(ck, nrhs)) {
+          ++k;
+          break;
+        }
+      }
+      launch_arnoldi_solve(ck.st, nrhs, st);
+      launch_maxpy<T, T>(xo, cs_, Vb, vsj, vsr, k, ck.y.get<cx<double>>(), m, 1.0, osz(), nrhs, nullptr, st);
+    }
+    // x_e = D_ee^{-1} (y_e - D_eo x_o)
+    launch_coarse_stencil<T, S>(te.get<cx<T>>(), esz(), 0, g.neven, ycv, cs_, nullptr, 0, 0, (T)0, xo, cs_, g.neven,
+                                (T)-1, C, g, nrhs, st);
+    launch_block_matvec<T>(xcv, cs_, Dinv.get<cx<T>>(), te.get<cx<T>>(), esz(), g.neven, g.nc, nrhs, st);
+    check_launch("coarse solve");
+    ++coarse_calls;
+    coarse_its_total += its;
+    coarse_its_max = std::max(coarse_its_max, its);
+    return its;
+  }
+
+  // -------------------------------------------------------------- V-cycle
+  // x = M^{-1} y (Alg. 1): coarse-grid correction then SAP from it
+  void vcycle(cx<T>* x, const cx<T>* y, int nrhs) {
+    launch_restrict<T, S>(yc.get<cx<T>>(), csz(), g.nc, y, fsz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    coarse_solve(xc.get<cx<T>>(), yc.get<cx<T>>(), nrhs);
+    launch_prolong<T, S>(x, fsz(), xc.get<cx<T>>(), csz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    sap(x, y, nrhs, c->p.nu);
+    check_launch("vcycle");
+  }
+
+  // ---------------------------------------------------------------- setup
+  void normalise(cx<T>* v, int n) {
+    launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), v, 0, fsz(), 1, v, fsz(), fsz(), n, nullptr,
+                   st);
+    HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
+    launch_inv_norm(ck.inv_h.get<double>(), ck.n2.get<cx<double>>(), n, c->status.get<int>(), st);
+    launch_scale<T, T>(v, fsz(), v, fsz(), ck.inv_h.get<double>(), fsz(), n, nullptr, st);
+    int stat = 0;
+    HIPCK(hipMemcpyAsync(c->h_flags, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    c->sync();
+    stat = c->h_flags[0];
+    if (stat) throw Fail{DDAMG_ENUMERIC, "test vector with zero or non-finite norm"};
+  }
+
+  // Alg. 5 from an orthonormal FP64 basis Wd: store R (storage S), build
+  // D_c = R D P from the stored basis, fill backward couplings by Eq. dagger,
+  // quantise, and invert the even self blocks.
+  void build_coarse_from(cx<double>* Wd) {
+    launch_quantize_basis<S>(Wq.get<stc_t<S>>(), Wsc.get<float>(), Wd, g, st);
+    const size_t nc = g.nc, nn = nc * nc;
+    DevBuf Dacc, Wt, Z;
+    cx<T>* D = Dacc.alloc<cx<T>>((size_t)g.nblocks * 9 * nn);
+    HIPCK(hipMemsetAsync(D, 0, sizeof(cx<T>) * g.nblocks * 9 * nn, st));
+    cx<T>* Wtp = Wt.alloc<cx<T>>((size_t)g.ntv * fsz());
+    launch_dequantize_basis<T, S>(Wtp, bv(), g, st);
+    const int CH = std::min(g.ntv, 8);
+    cx<T>* Zp = Z.alloc<cx<T>>((size_t)CH * fsz());
+    for (int hp = 0; hp < 2; ++hp)
+      for (int a0 = 0; a0 < g.ntv; a0 += CH) {
+        const int na = std::min(CH, g.ntv - a0);
+        const cx<T>* in = Wtp + (size_t)a0 * fsz();
+        for (int piece = 0; piece < 5; ++piece) {
+          const int mode = piece == 0 ? DS_BLOCK : DS_CROSS_FWD;
+          const int mu = piece == 0 ? 0 : piece - 1;
+          const int slot = piece == 0 ? 0 : 1 + 2 * mu;
+          launch_dslash<T, T, T, T>(Zp, in, gva, g, na, mode, mu, hp, fsz(), fsz(), st);
+          cx<T>* out = D + (size_t)slot * nn + (size_t)(hp * g.ntv + a0) * nc;
+          launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, c->b2i.get<int>(), na, st);
+        }
+      }
+    launch_dagger_fill<T>(D, c->nbr.get<int>(), g, st);
+    launch_quantize_coarse<T, S>(Dq.get<stc_t<S>>(), Dsc.get<float>(), D, g, st);
+    HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
+    launch_invert_even_blocks<T, S>(Dinv.get<cx<T>>(), cv(), g, c->status.get<int>(), st);
+    check_launch("build coarse");
+    int stat = 0;
+    HIPCK(hipMemcpyAsync(&stat, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    c->sync();
+    if (stat) throw Fail{DDAMG_ENUMERIC, "singular even self-coupling block of D_c"};
+  }
+
+  // Gram-Schmidt of the current test vectors on every aggregate, then D_c
+  void build_coarse() {
+    DevBuf Wd;
+    cx<double>* W = Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
+    launch_copy<double, T>(W, fsz(), tv.get<cx<T>>(), fsz(), fsz(), g.ntv, st);
+    HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
+    launch_aggregate_qr(W, g, c->status.get<int>(), st);
+    check_launch("aggregate qr");
+    int stat = 0;
+    HIPCK(hipMemcpyAsync(&stat, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    c->sync();
+    if (stat) throw Fail{DDAMG_ENUMERIC, "rank-deficient aggregate in the Gram-Schmidt of the test vectors"};
+    build_coarse_from(W);
+  }
+
+  void setup(const double* tv_canon) override {
+    const int n = g.ntv;
+    cx<T>* V = tv.get<cx<T>>();
+    launch_spinor_to_internal<T>(V, reinterpret_cast<const cx<double>*>(tv_canon), g, n, st);
+    // initial setup: smoother with N_smoother = 1, 2, 3 from a zero guess
+    for (int k = 1; k <= 3; ++k) {
+      launch_copy<T, T>(fy.get<cx<T>>(), fsz(), V, fsz(), fsz(), n, st);
+      HIPCK(hipMemsetAsync(V, 0, sizeof(cx<T>) * fsz() * n, st));
+      sap(V, fy.get<cx<T>>(), n, k);
+    }
+    build_coarse();
+    normalise(V, n);
+    // iterative setup: every test vector replaced by the V-cycle applied to it
+    for (int i = 0; i < c->p.n_setup; ++i) {
+      launch_copy<T, T>(fy.get<cx<T>>(), fsz(), V, fsz(), fsz(), n, st);
+      vcycle(V, fy.get<cx<T>>(), n);
+      normalise(V, n);
+      build_coarse();
+    }
+    c->sync();
+  }
+
+  void import_basis(const double* Wc) override {
+    DevBuf Wd;
+    cx<double>* W = Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
+    launch_spinor_to_internal<double>(W, reinterpret_cast<const cx<double>*>(Wc), g, g.ntv, st);
+    launch_copy<T, double>(tv.get<cx<T>>(), fsz(), W, fsz(), fsz(), g.ntv, st);
+    build_coarse_from(W);
+  }
+
+  void export_basis(double* Wc) override {
+    DevBuf Wt;
+    cx<double>* W = Wt.alloc<cx<double>>((size_t)g.ntv * fsz());
+    launch_dequantize_basis<double, S>(W, bv(), g, st);
+    launch_spinor_to_canonical<double>(reinterpret_cast<cx<double>*>(Wc), W, g, g.ntv, st);
+    c->sync();
+  }
+  void export_tv(double* out) override {
+    launch_spinor_to_canonical<T>(reinterpret_cast<cx<double>*>(out), tv.get<cx<T>>(), g, g.ntv, st);
+    c->sync();
+  }
+  void export_coarse(double* out) override {
+    launch_export_coarse<T, S>(reinterpret_cast<cx<double>*>(out), cv(), g, c->i2b.get<int>(), st);
+    c->sync();
+  }
+
+  void vcycle_canon(double* x, const double* y, int nrhs) override {
+    launch_spinor_to_internal<T>(fy.get<cx<T>>(), reinterpret_cast<const cx<double>*>(y), g, nrhs, st);
+    vcycle(fx.get<cx<T>>(), fy.get<cx<T>>(), nrhs);
+    launch_spinor_to_canonical<T>(reinterpret_cast<cx<double>*>(x), fx.get<cx<T>>(), g, nrhs, st);
+  }
+
+  void coarse_internal(void* out, const void* in, int nrhs) override {
+    launch_coarse_stencil<T, S>(static_cast<cx<T>*>(out), csz(), 0, g.nblocks, nullptr, 0,
+                                static_cast<const cx<T>*>(in), csz(), 0, (T)1, static_cast<const cx<T>*>(in), csz(), 0,
+                                (T)1, cv(), g, nrhs, st);
+  }
+  void coarse_canon(double* out, const double* in, int nrhs) override {
+    launch_coarse_to_internal<T>(yc.get<cx<T>>(), reinterpret_cast<const cx<double>*>(in), g, c->b2i.get<int>(), nrhs,
+                                 st);
+    coarse_internal(xc.get<cx<T>>(), yc.get<cx<T>>(), nrhs);
+    launch_coarse_to_canonical<T>(reinterpret_cast<cx<double>*>(out), xc.get<cx<T>>(), g, c->b2i.get<int>(), nrhs, st);
+  }
+  void restrict_canon(double* ycn, const double* y, int nrhs) override {
+    launch_spinor_to_internal<T>(fy.get<cx<T>>(), reinterpret_cast<const cx<double>*>(y), g, nrhs, st);
+    launch_restrict<T, S>(yc.get<cx<T>>(), csz(), g.nc, fy.get<cx<T>>(), fsz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    launch_coarse_to_canonical<T>(reinterpret_cast<cx<double>*>(ycn), yc.get<cx<T>>(), g, c->b2i.get<int>(), nrhs, st);
+  }
+  void prolong_canon(double* x, const double* xcn, int nrhs) override {
+    launch_coarse_to_internal<T>(xc.get<cx<T>>(), reinterpret_cast<const cx<double>*>(xcn), g, c->b2i.get<int>(), nrhs,
+                                 st);
+    launch_prolong<T, S>(fx.get<cx<T>>(), fsz(), xc.get<cx<T>>(), csz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    launch_spinor_to_canonical<T>(reinterpret_cast<cx<double>*>(x), fx.get<cx<T>>(), g, nrhs, st);
+  }
+
+  // ------------------------------------------------------- outer FGMRES
+  void ensure_outer(int m, int nrhs) {
+    if (m == outer_m && nrhs <= outer_r) return;
+    outer_m = m;
+    outer_r = nrhs;
+    const size_t n = fsz();
+    oV.alloc<cx<double>>((size_t)(m + 1) * nrhs * n);
+    oZ.alloc<cx<T>>((size_t)m * nrhs * n);
+    ow.alloc<cx<double>>((size_t)nrhs * n);
+    of.alloc<cx<double>>((size_t)nrhs * n);
+    ou.alloc<cx<double>>((size_t)nrhs * n);
+    ok.alloc(m, nrhs, n);
+  }
+
+  int solve(double* u_canon, const double* f_canon, int nrhs, double tol) override {
+    const int m = c->p.outer_restart;
+    ensure_outer(m, nrhs);
+    const size_t n = fsz();
+    const size_t vsj = (size_t)outer_r * n;  // stride between basis vectors
+    cx<double>* V = oV.get<cx<double>>();
+    cx<T>* Z = oZ.get<cx<T>>();
+    cx<double>* w = ow.get<cx<double>>();
+    cx<double>* f = of.get<cx<double>>();
+    cx<double>* u = ou.get<cx<double>>();
+    const GaugeView<double> g64 = c->gv64();
+    launch_spinor_to_internal<double>(f, reinterpret_cast<const cx<double>*>(f_canon), g, nrhs, st);
+    launch_spinor_to_internal<double>(u, reinterpret_cast<const cx<double>*>(u_canon), g, nrhs, st);
+    // ||f||
+    launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), f, 0, n, 1, f, n, n, nrhs, nullptr, st);
+    std::vector<cx<double>> fn2(nrhs), rn2(nrhs);
+    HIPCK(hipMemcpyAsync(c->h_cx, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost, st));
+    c->sync();
+    std::copy(c->h_cx, c->h_cx + nrhs, fn2.begin());
+    std::vector<double> fnorm(nrhs), abstol(nrhs), zero_scale(nrhs, 1.0);
+    bool any_zero = false;
+    for (int r = 0; r < nrhs; ++r) {
+      fnorm[r] = std::sqrt(std::max(fn2[r].r, 0.0));
+      if (!std::isfinite(fnorm[r])) throw Fail{DDAMG_ENUMERIC, "non-finite right-hand side"};
+      abstol[r] = tol * fnorm[r];
+      if (fnorm[r] == 0.0) {
+        zero_scale[r] = 0.0;  // f = 0: the solution is u = 0
+        any_zero = true;
+      }
+    }
+    std::copy(zero_scale.begin(), zero_scale.end(), c->h_dbl);
+    std::copy(abstol.begin(), abstol.end(), c->h_dbl + 64);
+    HIPCK(hipMemcpyAsync(ok.est.get<double>(), c->h_dbl, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(ok.abstol.get<double>(), c->h_dbl + 64, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    if (any_zero) launch_scale<double, double>(u, n, u, n, ok.est.get<double>(), n, nrhs, nullptr, st);
+    int its = 0, restarts = 0;
+    bool converged = false;
+    std::vector<double> relres(nrhs, 0.0);
+    for (;;) {
+      // true residual r = f - D u in FP64, into V_0
+      launch_dslash<double, double, double, double>(w, u, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
+      launch_sub<double>(V, n, f, n, w, n, n, nrhs, st);
+      launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), V, 0, n, 1, V, n, n, nrhs, nullptr,
+                          st);
+      HIPCK(hipMemcpyAsync(c->h_cx, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost, st));
+      c->sync();
+      std::copy(c->h_cx, c->h_cx + nrhs, rn2.begin());
+      bool all = true;
+      for (int r = 0; r < nrhs; ++r) {
+        double rn = std::sqrt(std::max(rn2[r].r, 0.0));
+        if (!std::isfinite(rn)) throw Fail{DDAMG_ENUMERIC, "non-finite residual in the outer solve"};
+        relres[r] = fnorm[r] > 0.0 ? rn / fnorm[r] : 0.0;
+        if (fnorm[r] > 0.0 && rn > abstol[r]) all = false;
+      }
+      if (all) {
+        converged = true;
+        break;
+      }
+      if (its >= c->p.outer_maxit) break;
+      launch_arnoldi_start(ok.st, ok.n2.get<cx<double>>(), 1, nrhs, st);
+      launch_scale<double, double>(V, n, V, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
+      int k = 0;
+      for (; k < m && its < c->p.outer_maxit; ++k) {
+        cx<double>* vk = V + (size_t)k * vsj;
+        cx<T>* zk = Z + (size_t)k * vsj;
+        // z_k = M^{-1} v_k
+        launch_copy<T, double>(fy.get<cx<T>>(), n, vk, n, n, nrhs, st);
+        vcycle(zk, fy.get<cx<T>>(), nrhs);
+        // w = D z_k (FP64 operator)
+        cx<double>* wk = V + (size_t)(k + 1) * vsj;
+        if constexpr (std::is_same<T, double>::value)
+          launch_dslash<double, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
+        else
+          launch_dslash<float, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
+        cgs2(ok, V, vsj, n, k, wk, n, n, nrhs);
+        launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), ok.h2.get<cx<double>>(), ok.ldh,
+                              ok.n2.get<cx<double>>(), 1, nrhs, st);
+        launch_scale<double, double>(wk, n, wk, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
+        ++its;
+        if (!read_any_active(ok, nrhs)) {
+          ++k;
+          break;
+        }
+      }
+      launch_arnoldi_solve(ok.st, nrhs, st);
+      launch_maxpy<double, T>(u, n, Z, vsj, n, k, ok.y.get<cx<double>>(), m, 1.0, n, nrhs, nullptr, st);
+      ++restarts;
+    }
+    launch_spinor_to_canonical<double>(reinterpret_cast<cx<double>*>(u_canon), u, g, nrhs, st);
+    check_launch("solve");
+    c->sync();
+    ddamg_stats& s = c->stats;
+    s.outer_iterations = its;
+    s.outer_restarts = restarts;
+    s.nrhs = nrhs;
+    s.converged = converged ? 1 : 0;
+    for (int r = 0; r < 64; ++r) s.relres[r] = r < nrhs ? relres[r] : 0.0;
+    return converged ? DDAMG_OK : DDAMG_NOT_CONVERGED;
+  }
+};
+
+int fail_to_code(ddamg_ctx* c, const Fail& f) {
+  if (c) c->err = f.msg;
+  return f.code;
+}
+
+bool is_even_split(const ddamg_params* p, int mu) { return (p->L[mu] / p->block[mu]) % 2 == 0; }
+
+int validate(const ddamg_params* p, std::string& why) {
+  if (!p) {
+    why = "params is NULL";
+    return DDAMG_EARG;
+  }
+  int64_t V = 1, vb = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (p->L[mu] < 1 || p->block[mu] < 1) {
+      why = "lattice and block extents must be positive";
+      return DDAMG_EARG;
+    }
+    if (p->L[mu] % p->block[mu]) {
+      why = "block extent must divide the lattice extent in direction " + std::to_string(mu);
+      return DDAMG_EARG;
+    }
+    if (!is_even_split(p, mu)) {
+      why = "the number of blocks in direction " + std::to_string(mu) +
+            " must be even (red/black SAP and coarse even/odd)";
+      return DDAMG_EARG;
+    }
+    V *= p->L[mu];
+    vb *= p->block[mu];
+  }
+  if (V > (int64_t)1 << 28) {
+    why = "lattice volume too large";
+    return DDAMG_EARG;
+  }
+  if (vb > 256) {
+    why = "block volume must be at most 256 sites";
+    return DDAMG_EARG;
+  }
+  if (p->ntv < 1 || p->ntv > 32) {
+    why = "ntv must be in [1, 32]";
+    return DDAMG_EARG;
+  }
+  if (6 * vb < p->ntv) {
+    why = "aggregates too small: 6 * block volume < ntv";
+    return DDAMG_EARG;
+  }
+  if (p->n_setup < 0 || p->nu < 0 || p->n_mr < 0) {
+    why = "n_setup, nu and n_mr must be non-negative";
+    return DDAMG_EARG;
+  }
+  if (p->coarse_restart < 1 || p->coarse_restart > 64 || p->outer_restart < 1 || p->outer_restart > 64) {
+    why = "restart lengths must be in [1, 64]";
+    return DDAMG_EARG;
+  }
+  if (p->coarse_maxit < 1 || p->outer_maxit < 1 || p->coarse_fixed_its < 0) {
+    why = "iteration limits must be positive";
+    return DDAMG_EARG;
+  }
+  if (p->coarse_fixed_its == 0 && !(p->coarse_tol > 0.0)) {
+    why = "coarse_tol must be positive";
+    return DDAMG_EARG;
+  }
+  if (p->prec != DDAMG_FP64 && p->prec != DDAMG_FP32 && p->prec != DDAMG_MIXED16) {
+    why = "unknown precision";
+    return DDAMG_EARG;
+  }
+  if (p->max_rhs < 1 || p->max_rhs > 64) {
+    why = "max_rhs must be in [1, 64]";
+    return DDAMG_EARG;
+  }
+  if (!std::isfinite(p->m0) || !std::isfinite(p->csw)) {
+    why = "m0 and csw must be finite";
+    return DDAMG_EARG;
+  }
+  return DDAMG_OK;
+}
+
+void build_tables(ddamg_ctx* c) {
+  const Geom& g = c->g;
+  std::vector<int> colour(g.nblocks), b2i(g.nblocks), i2b(g.nblocks), nbr((size_t)g.nblocks * 9);
+  std::vector<int> cb;
+  cb.reserve(g.nblocks);
+  auto bcoord = [&](int b, int bc[4]) {
+    bc[0] = b % g.NB[0];
+    b /= g.NB[0];
+    bc[1] = b % g.NB[1];
+    b /= g.NB[1];
+    bc[2] = b % g.NB[2];
+    bc[3] = b / g.NB[2];
+  };
+  auto bindex = [&](const int bc[4]) { return bc[0] + g.NB[0] * (bc[1] + g.NB[1] * (bc[2] + g.NB[2] * bc[3])); };
+  for (int b = 0; b < g.nblocks; ++b) {
+    int bc[4];
+    bcoord(b, bc);
+    colour[b] = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+  }
+  for (int col = 0; col < 2; ++col)
+    for (int b = 0; b < g.nblocks; ++b)
+      if (colour[b] == col) cb.push_back(b);
+  int ne = 0;
+  for (int b = 0; b < g.nblocks; ++b)
+    if (colour[b] == 0) i2b[ne++] = b;
+  int k = ne;
+  for (int b = 0; b < g.nblocks; ++b)
+    if (colour[b] == 1) i2b[k++] = b;
+  for (int i = 0; i < g.nblocks; ++i) b2i[i2b[i]] = i;
+  for (int b = 0; b < g.nblocks; ++b) {
+    int bc[4];
+    bcoord(b, bc);
+    const int ci = b2i[b];
+    nbr[(size_t)ci * 9] = ci;
+    for (int mu = 0; mu < 4; ++mu)
+      for (int d = 0; d < 2; ++d) {
+        int e[4] = {bc[0], bc[1], bc[2], bc[3]};
+        e[mu] = (e[mu] + (d == 0 ? 1 : -1) + g.NB[mu]) % g.NB[mu];
+        nbr[(size_t)ci * 9 + 1 + 2 * mu + d] = b2i[bindex(e)];
+      }
+  }
+  c->g.neven = ne;
+  auto up = [&](DevBuf& d, const std::vector<int>& h) {
+    d.alloc<int>(h.size());
+    HIPCK(hipMemcpy(d.get<int>(), h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+  };
+  up(c->colour_blocks, cb);
+  up(c->b2i, b2i);
+  up(c->i2b, i2b);
+  up(c->nbr, nbr);
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+void ddamg_default_params(ddamg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  for (int mu = 0; mu < 4; ++mu) {
+    p->L[mu] = 8;
+    p->block[mu] = 4;
+  }
+  p->m0 = 0.0;
+  p->csw = 1.0;
+  p->ntv = 24;
+  p->n_setup = 3;
+  p->nu = 3;
+  p->n_mr = 4;
+  p->coarse_tol = 0.05;
+  p->coarse_restart = 30;
+  p->coarse_maxit = 300;
+  p->coarse_fixed_its = 0;
+  p->outer_restart = 20;
+  p->outer_maxit = 2000;
+  p->prec = DDAMG_MIXED16;
+  p->max_rhs = 12;
+}
+
+int ddamg_validate_params(const ddamg_params* p, char* msg, size_t msg_len) {
+  std::string why;
+  int rc = validate(p, why);
+  if (msg && msg_len) {
+    std::snprintf(msg, msg_len, "%s", why.c_str());
+  }
+  return rc;
+}
+
+int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg_ctx** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return DDAMG_EARG;
+  }
+  *out = nullptr;
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) {
+    g_create_error = why;
+    return rc;
+  }
+  if (!gauge) {
+    g_create_error = "gauge is NULL";
+    return DDAMG_EARG;
+  }
+  std::unique_ptr<ddamg_ctx> c(new ddamg_ctx());
+  try {
+    c->p = *p;
+    c->st = static_cast<hipStream_t>(stream);
+    Geom& g = c->g;
+    g.V = 1;
+    g.vblock = 1;
+    g.nblocks = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      g.L[mu] = p->L[mu];
+      g.bs[mu] = p->block[mu];
+      g.NB[mu] = p->L[mu] / p->block[mu];
+      g.V *= g.L[mu];
+      g.vblock *= g.bs[mu];
+      g.nblocks *= g.NB[mu];
+    }
+    g.ntv = p->ntv;
+    g.nc = 2 * p->ntv;
+    build_tables(c.get());
+    HIPCK(hipHostMalloc((void**)&c->h_flags, 64 * sizeof(int), hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void**)&c->h_dbl, 128 * sizeof(double), hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void**)&c->h_cx, 64 * sizeof(cx<double>), hipHostMallocDefault));
+    c->status.alloc<int>(1);
+    const size_t V = g.V;
+    c->U64.alloc<cx<double>>(36 * V);
+    c->A64.alloc<double>(72 * V);
+    c->U32.alloc<cx<float>>(36 * V);
+    c->A32.alloc<float>(72 * V);
+    c->Uh.alloc<__half2>(36 * V);
+    c->Uhs.alloc<float>(V);
+    c->Ah.alloc<__half>(72 * V);
+    c->Ahs.alloc<float>(V);
+    launch_gauge_import(c->U64.get<cx<double>>(), reinterpret_cast<const cx<double>*>(gauge), g, c->st);
+    launch_clover_build(c->A64.get<double>(), c->U64.get<cx<double>>(), g, p->m0, p->csw, c->st);
+    launch_quantize_gauge<float>(c->U32.get<cx<float>>(), nullptr, c->A32.get<float>(), nullptr,
+                                 c->U64.get<cx<double>>(), c->A64.get<double>(), g, c->st);
+    launch_quantize_gauge<__half>(c->Uh.get<__half2>(), c->Uhs.get<float>(), c->Ah.get<__half>(), c->Ahs.get<float>(),
+                                  c->U64.get<cx<double>>(), c->A64.get<double>(), g, c->st);
+    check_launch("create");
+    switch (p->prec) {
+      case DDAMG_FP64:
+        c->sol.reset(new Solver<double, double>(c.get(), c->gv64(), c->gv64()));
+        break;
+      case DDAMG_FP32:
+        c->sol.reset(new Solver<float, float>(c.get(), c->gv32(), c->gv32()));
+        break;
+      default:
+        c->sol.reset(new Solver<float, __half>(c.get(), c->gvh(), c->gv32()));
+        break;
+    }
+    c->sync();
+  } catch (const Fail& f) {
+    g_create_error = f.msg;
+    c->free_pinned();
+    return f.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    c->free_pinned();
+    return DDAMG_ENOMEM;
+  }
+  *out = c.release();
+  return DDAMG_OK;
+}
+
+int ddamg_destroy(ddamg_ctx* c) {
+  if (!c) return DDAMG_EARG;
+  (void)hipStreamSynchronize(c->st);
+  c->sol.reset();
+  c->free_pinned();
+  delete c;
+  return DDAMG_OK;
+}
+
+const char* ddamg_last_error(const ddamg_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+#define GUARD_BEGIN try {
+#define GUARD_END                            \
+  }                                          \
+  catch (const Fail& f) {                    \
+    return fail_to_code(c, f);               \
+  }                                          \
+  catch (const std::exception& e) {          \
+    c->err = e.what();                       \
+    return DDAMG_ENOMEM;                     \
+  }
+
+static int need_setup(ddamg_ctx* c) {
+  if (!c->setup_done) {
+    c->err = "call mg_setup (or ddamg_import_basis) first";
+    return DDAMG_ESTATE;
+  }
+  return 0;
+}
+static int check_rhs(ddamg_ctx* c, int nrhs) {
+  if (nrhs < 1 || nrhs > c->p.max_rhs) {
+    c->err = "nrhs must be in [1, max_rhs]";
+    return DDAMG_EARG;
+  }
+  return 0;
+}
+
+int mg_setup(ddamg_ctx* c, const double* tv_init) {
+  if (!c) return DDAMG_EARG;
+  if (!tv_init) {
+    c->err = "tv_init is NULL";
+    return DDAMG_EARG;
+  }
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  c->setup_done = false;
+  c->sol->setup(tv_init);
+  c->setup_done = true;
+  c->stats.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_import_basis(ddamg_ctx* c, const double* W) {
+  if (!c) return DDAMG_EARG;
+  if (!W) {
+    c->err = "W is NULL";
+    return DDAMG_EARG;
+  }
+  GUARD_BEGIN
+  c->setup_done = false;
+  c->sol->import_basis(W);
+  c->setup_done = true;
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_export_basis(ddamg_ctx* c, double* W) {
+  if (!c || !W) return DDAMG_EARG;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->export_basis(W);
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_export_tv(ddamg_ctx* c, double* tv) {
+  if (!c || !tv) return DDAMG_EARG;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->export_tv(tv);
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_export_coarse(ddamg_ctx* c, double* Dc) {
+  if (!c || !Dc) return DDAMG_EARG;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->export_coarse(Dc);
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_export_clover(ddamg_ctx* c, double* A) {
+  if (!c || !A) return DDAMG_EARG;
+  GUARD_BEGIN
+  launch_clover_export(reinterpret_cast<cx<double>*>(A), c->A64.get<double>(), c->g, c->st);
+  check_launch("export clover");
+  c->sync();
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int mg_apply(ddamg_ctx* c, double* x, const double* y, int nrhs) {
+  if (!c) return DDAMG_EARG;
+  if (!x || !y || x == y) {
+    c->err = "x and y must be distinct non-NULL pointers";
+    return DDAMG_EARG;
+  }
+  if (int e = check_rhs(c, nrhs)) return e;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->vcycle_canon(x, y, nrhs);
+  check_launch("mg_apply");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int dirac_apply_internal(ddamg_ctx* c, void* out, const void* in, int nrhs, int prec) {
+  if (!c) return DDAMG_EARG;
+  if (!out || !in || out == in) {
+    c->err = "out and in must be distinct non-NULL pointers";
+    return DDAMG_EARG;
+  }
+  if (nrhs < 1 || nrhs > 65535) {
+    c->err = "nrhs out of range";
+    return DDAMG_EARG;
+  }
+  GUARD_BEGIN
+  const Geom& g = c->g;
+  const size_t n = (size_t)12 * g.V;
+  switch (prec) {
+    case DDAMG_FP64:
+      launch_dslash<double, double, double, double>(static_cast<cx<double>*>(out), static_cast<const cx<double>*>(in),
+                                                    c->gv64(), g, nrhs, DS_FULL, 0, -1, n, n, c->st);
+      break;
+    case DDAMG_FP32:
+      launch_dslash<float, float, float, float>(static_cast<cx<float>*>(out), static_cast<const cx<float>*>(in),
+                                                c->gv32(), g, nrhs, DS_FULL, 0, -1, n, n, c->st);
+      break;
+    case DDAMG_MIXED16:
+      launch_dslash<float, float, __half, float>(static_cast<cx<float>*>(out), static_cast<const cx<float>*>(in),
+                                                 c->gvh(), g, nrhs, DS_FULL, 0, -1, n, n, c->st);
+      break;
+    default:
+      c->err = "unknown precision";
+      return DDAMG_EARG;
+  }
+  check_launch("dirac_apply_internal");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int dirac_apply(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec) {
+  if (!c) return DDAMG_EARG;
+  if (!out || !in || out == in) {
+    c->err = "out and in must be distinct non-NULL pointers";
+    return DDAMG_EARG;
+  }
+  if (int e = check_rhs(c, nrhs)) return e;
+  if (prec != DDAMG_FP64 && prec != DDAMG_FP32 && prec != DDAMG_MIXED16) {
+    c->err = "unknown precision";
+    return DDAMG_EARG;
+  }
+  GUARD_BEGIN
+  const Geom& g = c->g;
+  c->ensure_stage(nrhs);
+  const cx<double>* cin = reinterpret_cast<const cx<double>*>(in);
+  cx<double>* cout = reinterpret_cast<cx<double>*>(out);
+  if (prec == DDAMG_FP64) {
+    cx<double>* a = c->stage_in.get<cx<double>>();
+    cx<double>* b = c->stage_out.get<cx<double>>();
+    launch_spinor_to_internal<double>(a, cin, g, nrhs, c->st);
+    int rc = dirac_apply_internal(c, b, a, nrhs, prec);
+    if (rc) return rc;
+    launch_spinor_to_canonical<double>(cout, b, g, nrhs, c->st);
+  } else {
+    cx<float>* a = c->stage_in.get<cx<float>>();
+    cx<float>* b = c->stage_out.get<cx<float>>();
+    launch_spinor_to_internal<float>(a, cin, g, nrhs, c->st);
+    int rc = dirac_apply_internal(c, b, a, nrhs, prec);
+    if (rc) return rc;
+    launch_spinor_to_canonical<float>(cout, b, g, nrhs, c->st);
+  }
+  check_launch("dirac_apply");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int coarse_apply(ddamg_ctx* c, double* out, const double* in, int nrhs) {
+  if (!c) return DDAMG_EARG;
+  if (!out || !in || out == in) {
+    c->err = "out and in must be distinct non-NULL pointers";
+    return DDAMG_EARG;
+  }
+  if (int e = check_rhs(c, nrhs)) return e;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->coarse_canon(out, in, nrhs);
+  check_launch("coarse_apply");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int coarse_apply_internal(ddamg_ctx* c, void* out, const void* in, int nrhs) {
+  if (!c) return DDAMG_EARG;
+  if (!out || !in || out == in) {
+    c->err = "out and in must be distinct non-NULL pointers";
+    return DDAMG_EARG;
+  }
+  if (nrhs < 1 || nrhs > 65535) {
+    c->err = "nrhs out of range";
+    return DDAMG_EARG;
+  }
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->coarse_internal(out, in, nrhs);
+  check_launch("coarse_apply_internal");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int mg_restrict(ddamg_ctx* c, double* yc, const double* y, int nrhs) {
+  if (!c) return DDAMG_EARG;
+  if (!yc || !y) {
+    c->err = "NULL pointer";
+    return DDAMG_EARG;
+  }
+  if (int e = check_rhs(c, nrhs)) return e;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->restrict_canon(yc, y, nrhs);
+  check_launch("mg_restrict");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int mg_prolong(ddamg_ctx* c, double* x, const double* xc, int nrhs) {
+  if (!c) return DDAMG_EARG;
+  if (!x || !xc) {
+    c->err = "NULL pointer";
+    return DDAMG_EARG;
+  }
+  if (int e = check_rhs(c, nrhs)) return e;
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->prolong_canon(x, xc, nrhs);
+  check_launch("mg_prolong");
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int solve(ddamg_ctx* c, double* u, const double* f, int nrhs, double tol, ddamg_stats* st) {
+  if (!c) return DDAMG_EARG;
+  if (!u || !f || u == f) {
+    c->err = "u and f must be distinct non-NULL pointers";
+    return DDAMG_EARG;
+  }
+  if (int e = check_rhs(c, nrhs)) return e;
+  if (!(tol > 0.0) || !(tol < 1.0)) {
+    c->err = "tol must be in (0, 1)";
+    return DDAMG_EARG;
+  }
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = c->sol->solve(u, f, nrhs, tol);
+  c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st) ddamg_get_stats(c, st);
+  return rc;
+  GUARD_END
+}
+
+int ddamg_get_stats(const ddamg_ctx* c, ddamg_stats* st) {
+  if (!c || !st) return DDAMG_EARG;
+  *st = c->stats;
+  if (c->sol) c->sol->coarse_stats(st->coarse_solves, st->coarse_iterations, st->coarse_iterations_max);
+  return DDAMG_OK;
+}
+
+int ddamg_reset_stats(ddamg_ctx* c) {
+  if (!c) return DDAMG_EARG;
+  if (c->sol) c->sol->reset_coarse_stats();
+  return DDAMG_OK;
+}
+
+int64_t ddamg_volume(const ddamg_ctx* c) { return c ? (int64_t)c->g.V : -1; }
+int32_t ddamg_nblocks(const ddamg_ctx* c) { return c ? c->g.nblocks : -1; }
+
+}  // extern "C"

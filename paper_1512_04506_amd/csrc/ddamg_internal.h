@@ -1,0 +1,274 @@
+// Internal declarations of the gfx950 DD-alpha-AMG library: complex and
+// storage types, lattice geometry, field views and the host-side launchers
+// of every kernel.  Not part of the public ABI (include/ddamg.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <cstddef>
+#include <cstdint>
+#include <type_traits>
+
+namespace ddamg {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T r, i;
+};
+
+template <typename T>
+__host__ __device__ inline cx<T> mk(T r, T i) { cx<T> c; c.r = r; c.i = i; return c; }
+template <typename T>
+__host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.r + b.r, a.i + b.i); }
+template <typename T>
+__host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.r - b.r, a.i - b.i); }
+template <typename T>
+__host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk(a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r);
+}
+template <typename T>
+__host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return mk(s * a.r, s * a.i); }
+template <typename T>
+__host__ __device__ inline cx<T> conj(cx<T> a) { return mk(a.r, -a.i); }
+// conj(a) * b
+template <typename T>
+__host__ __device__ inline cx<T> cmulc(cx<T> a, cx<T> b) {
+  return mk(a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r);
+}
+template <typename T>
+__host__ __device__ inline cx<T> times_i(cx<T> a) { return mk(-a.i, a.r); }
+template <typename T>
+__host__ __device__ inline cx<T> times_mi(cx<T> a) { return mk(a.i, -a.r); }
+template <typename T>
+__host__ __device__ inline cx<T> neg(cx<T> a) { return mk(-a.r, -a.i); }
+template <typename T, typename U>
+__host__ __device__ inline cx<T> cvt(cx<U> a) { return mk((T)a.r, (T)a.i); }
+
+// ------------------------------------------------------- storage formats
+// Static fields (links, clover, aggregate basis, coarse operator) are
+// stored as S = double, float or __half.  Half storage carries one FP32
+// scale per group (stored value = x / scale, scale = max |re|, |im| of the
+// group) so that every group fits the FP16 range with full relative
+// resolution.
+template <typename S> struct stc;
+template <> struct stc<double> { using type = cx<double>; };
+template <> struct stc<float> { using type = cx<float>; };
+template <> struct stc<__half> { using type = __half2; };
+template <typename S> using stc_t = typename stc<S>::type;
+
+template <typename S> constexpr bool is_half() { return std::is_same<S, __half>::value; }
+
+template <typename T>
+__device__ inline cx<T> ldc(const cx<double>* p, size_t i) { cx<double> v = p[i]; return mk((T)v.r, (T)v.i); }
+template <typename T>
+__device__ inline cx<T> ldc(const cx<float>* p, size_t i) { cx<float> v = p[i]; return mk((T)v.r, (T)v.i); }
+template <typename T>
+__device__ inline cx<T> ldc(const __half2* p, size_t i) {
+  float2 f = __half22float2(p[i]);
+  return mk((T)f.x, (T)f.y);
+}
+template <typename T>
+__device__ inline T ldr(const double* p, size_t i) { return (T)p[i]; }
+template <typename T>
+__device__ inline T ldr(const float* p, size_t i) { return (T)p[i]; }
+template <typename T>
+__device__ inline T ldr(const __half* p, size_t i) { return (T)__half2float(p[i]); }
+
+__device__ inline void stc_store(cx<double>* p, size_t i, cx<double> v) { p[i] = v; }
+__device__ inline void stc_store(cx<float>* p, size_t i, cx<double> v) { p[i] = mk((float)v.r, (float)v.i); }
+__device__ inline void stc_store(__half2* p, size_t i, cx<double> v) {
+  p[i] = __floats2half2_rn((float)v.r, (float)v.i);
+}
+
+// ---------------------------------------------------------------- geometry
+struct Geom {
+  int L[4];      // lattice extents x, y, z, t
+  int bs[4];     // block extents
+  int NB[4];     // block-lattice extents
+  int V;         // sites
+  int vblock;    // sites per block
+  int nblocks;   // blocks = coarse sites
+  int ntv;       // test vectors
+  int nc;        // coarse components per site = 2 ntv
+  int neven;     // coarse sites of even parity (internal order: even first)
+};
+
+__host__ __device__ inline void site_coords(const Geom& g, int s, int c[4]) {
+  c[0] = s % g.L[0]; s /= g.L[0];
+  c[1] = s % g.L[1]; s /= g.L[1];
+  c[2] = s % g.L[2];
+  c[3] = s / g.L[2];
+}
+__host__ __device__ inline int site_index(const Geom& g, const int c[4]) {
+  return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+// lexicographic block index of a site
+__host__ __device__ inline int block_of(const Geom& g, const int c[4]) {
+  return c[0] / g.bs[0] + g.NB[0] * (c[1] / g.bs[1] + g.NB[1] * (c[2] / g.bs[2] + g.NB[2] * (c[3] / g.bs[3])));
+}
+// global site of local site l in lexicographic block b
+__host__ __device__ inline int block_site(const Geom& g, int b, int l, int c[4]) {
+  int bc[4];
+  bc[0] = b % g.NB[0]; b /= g.NB[0];
+  bc[1] = b % g.NB[1]; b /= g.NB[1];
+  bc[2] = b % g.NB[2];
+  bc[3] = b / g.NB[2];
+  int lc[4];
+  lc[0] = l % g.bs[0]; l /= g.bs[0];
+  lc[1] = l % g.bs[1]; l /= g.bs[1];
+  lc[2] = l % g.bs[2];
+  lc[3] = l / g.bs[2];
+  for (int m = 0; m < 4; ++m) c[m] = bc[m] * g.bs[m] + lc[m];
+  return site_index(g, c);
+}
+
+// Links [mu][9][V] (row-major 3x3 per link), clover [2][36][V]: per chirality
+// 6 real diagonal entries then the 15 upper off-diagonal entries (i < j,
+// row-major) as (re, im) pairs; row/col index = 3 * spin_in_chirality + colour.
+template <typename S>
+struct GaugeView {
+  const stc_t<S>* U;
+  const float* Usc;   // [V] link scale (half only)
+  const S* A;
+  const float* Asc;   // [V] clover scale (half only)
+};
+
+// Aggregate basis [ntv][12][V] complex + scale [ntv][V] (half only).
+template <typename S>
+struct BasisView {
+  const stc_t<S>* W;
+  const float* Wsc;
+};
+
+// Coarse operator, internal coarse-site order: [Nb][9][col][row] complex
+// (column-major blocks) + scale [Nb][9] (half only); neighbour table
+// nbr[Nb][9] in internal order.
+template <typename S>
+struct CoarseView {
+  const stc_t<S>* D;
+  const float* Dsc;
+  const int* nbr;
+};
+
+// dslash variants
+enum { DS_FULL = 0, DS_BLOCK = 1, DS_CROSS_FWD = 2, DS_CROSS_BWD = 3 };
+
+// ---------------------------------------------------------------- launchers
+// fields
+void launch_gauge_import(cx<double>* U, const cx<double>* canon, const Geom& g, hipStream_t st);
+void launch_clover_build(double* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st);
+template <typename S>
+void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, S* Aq, float* Asc, const cx<double>* U, const double* A,
+                           const Geom& g, hipStream_t st);
+template <typename T>
+void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st);
+template <typename T>
+void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st);
+void launch_clover_export(cx<double>* out, const double* A, const Geom& g, hipStream_t st);
+
+// dslash: out[r] = piece of D applied to in[r] (chi_in >= 0 keeps only that
+// chirality of the input; mu selects the direction of the cross variants).
+template <typename Tin, typename Tout, typename S, typename Tc>
+void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mode,
+                   int mu, int chi_in, size_t in_rstride, size_t out_rstride, hipStream_t st);
+
+// SAP: one colour phase of multiplicative Schwarz with n_mr MR steps per
+// block, in place on x, for nrhs fields.
+template <typename T, typename S>
+void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, const int* colour_blocks,
+                      int colour, int n_mr, int nrhs, hipStream_t st);
+
+// restriction / prolongation; coarse output addressed as
+// out[r * ostr_r + cint(b) * ostr_b + h * ntv + a]
+template <typename T, typename S>
+void launch_restrict(cx<T>* out, size_t ostr_r, size_t ostr_b, const cx<T>* y, size_t ystr, const BasisView<S>& bv,
+                     const Geom& g, const int* block_to_int, int nrhs, hipStream_t st);
+template <typename T, typename S>
+void launch_prolong(cx<T>* x, size_t xstr, const cx<T>* xc, size_t cstr, const BasisView<S>& bv, const Geom& g,
+                    const int* block_to_int, int nrhs, hipStream_t st);
+
+// coarse stencil: for internal output sites [out_first, out_first + nout):
+// out = add + cs * D_self xs + cn * sum_{slot>0} D_slot xn(nbr)
+// vectors are addressed as ptr[r * str + (ci - first) * nc + k].
+template <typename T, typename S>
+void launch_coarse_stencil(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T>* add, size_t astr,
+                           const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr,
+                           int xn_first, T cn, const CoarseView<S>& cv, const Geom& g, int nrhs, hipStream_t st);
+// out[k] = M[k] x[k] for dense nc x nc column-major blocks M (k < nsites)
+template <typename T>
+void launch_block_matvec(cx<T>* out, size_t ostr, const cx<T>* M, const cx<T>* x, size_t xstr, int nsites, int nc,
+                         int nrhs, hipStream_t st);
+
+// setup kernels
+void launch_aggregate_qr(cx<double>* W, const Geom& g, int* status, hipStream_t st);
+template <typename S>
+void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st);
+template <typename T, typename S>
+void launch_dequantize_basis(cx<T>* out, const BasisView<S>& bv, const Geom& g, hipStream_t st);
+template <typename T>
+void launch_dagger_fill(cx<T>* Dc, const int* nbr, const Geom& g, hipStream_t st);
+template <typename T, typename S>
+void launch_quantize_coarse(stc_t<S>* Dq, float* Dsc, const cx<T>* Dc, const Geom& g, hipStream_t st);
+template <typename T, typename S>
+void launch_invert_even_blocks(cx<T>* Dinv, const CoarseView<S>& cv, const Geom& g, int* status, hipStream_t st);
+template <typename T, typename S>
+void launch_export_coarse(cx<double>* out, const CoarseView<S>& cv, const Geom& g, const int* int_to_block,
+                          hipStream_t st);
+template <typename T>
+void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, const int* block_to_int, int nrhs,
+                               hipStream_t st);
+template <typename T>
+void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, const int* block_to_int, int nrhs,
+                                hipStream_t st);
+
+// BLAS on block vectors x[r * rstride + i], i < n, r < nrhs.
+// partial dots: part[(r * nvec + j) * nchunk + c]; final h[r * ldh + j].
+int blas_nchunks(size_t n);
+template <typename T>
+void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size_t vstride_j, size_t vstride_r,
+                 int nvec, const cx<T>* w, size_t wstride_r, size_t n, int nrhs, const int* active, hipStream_t st);
+// w[r] += sign * sum_j h[r * ldh + j] * V_j[r]
+template <typename Tw, typename Tv>
+void launch_maxpy(cx<Tw>* w, size_t wstride_r, const cx<Tv>* Vb, size_t vstride_j, size_t vstride_r, int nvec,
+                  const cx<double>* h, int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st);
+// y[r] = s[r] * x[r] (s real double, per rhs) ; y and x may alias
+template <typename Ty, typename Tx>
+void launch_scale(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, const double* s, size_t n, int nrhs,
+                  const int* active, hipStream_t st);
+// abstol[r] = tol * |n2[r]|^(1/2) (tol < 0 gives -1); s[r] = |n2[r]|^(-1/2)
+// with *status set to 1 if a norm is zero or not finite (nrhs <= 64)
+void launch_set_abstol(double* abstol, const cx<double>* n2, double tol, int nrhs, hipStream_t st);
+void launch_inv_norm(double* s, const cx<double>* n2, int nrhs, int* status, hipStream_t st);
+// y[r] = a[r] - b[r]
+template <typename T>
+void launch_sub(cx<T>* y, size_t ystr, const cx<T>* a, size_t astr, const cx<T>* b, size_t bstr, size_t n, int nrhs,
+                hipStream_t st);
+template <typename Ty, typename Tx>
+void launch_copy(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, size_t n, int nrhs, hipStream_t st);
+
+// Arnoldi / Givens state on the device (FP64).  Per rhs r: H[r][(m+1) * m]
+// column-major (H[r][k * (m+1) + j]), cs/sn[r][m], g[r][m+1].
+struct ArnoldiState {
+  cx<double>* H;
+  cx<double>* cs;
+  cx<double>* sn;
+  cx<double>* g;
+  cx<double>* y;       // [r][m] least-squares solution
+  double* est;         // [r] current residual estimate |g_{k+1}|
+  double* inv_h;       // [r] 1 / h_{k+1,k} (0 if breakdown or inactive)
+  double* abstol;      // [r] stop threshold (< 0: never)
+  int* active;         // [r]
+  int* kdone;          // [r] iterations done in this cycle
+  int m;
+};
+// start a cycle: g = (beta, 0, ...), active = beta > abstol (or beta > 0
+// when abstol < 0), kdone = 0, inv_h = 1 / beta; beta from norm2[r] = |.|^2
+void launch_arnoldi_start(ArnoldiState s, const cx<double>* norm2, int ldn, int nrhs, hipStream_t st);
+// column k: H[0..k, k] = h1 + h2, H[k+1, k] = sqrt(norm2), rotations, g,
+// est, convergence -> active, kdone
+void launch_arnoldi_column(ArnoldiState s, int k, const cx<double>* h1, const cx<double>* h2, int ldh,
+                           const cx<double>* norm2, int ldn, int nrhs, hipStream_t st);
+// y = H(1:kd, 1:kd)^{-1} g(1:kd) per rhs (upper triangular)
+void launch_arnoldi_solve(ArnoldiState s, int nrhs, hipStream_t st);
+
+}  // namespace ddamg

@@ -1,0 +1,187 @@
+// Per-site device helpers of the Wilson-clover operator shared by the
+// dslash and SAP kernels: spin projection/reconstruction of the hops, SU(3)
+// link loads, the clover block multiply, and one site of D or its pieces.
+//
+// In the chiral basis g_mu = [[0, X_mu], [X_mu^dag, 0]] with X_k = -i s_k
+// (Pauli s_k) and X_4 = -1, so
+//   (1 - g) psi = (h, -X^dag h),  h = psi_up - X psi_dn
+//   (1 + g) psi = (h,  X^dag h),  h = psi_up + X psi_dn
+// and each hop multiplies only the 2-spinor h by the link.
+#pragma once
+#include "ddamg_internal.h"
+
+namespace ddamg {
+namespace dev {
+
+template <typename T>
+struct Half2 {
+  cx<T> h[2][3];
+};
+
+// h = psi_up - X_mu psi_dn (FWD) or psi_up + X_mu psi_dn (BWD)
+template <int MU, bool FWD, typename T>
+__device__ inline void project(Half2<T>& o, const cx<T> p[4][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (MU == 0) {
+      o.h[0][c] = FWD ? p[0][c] + times_i(p[3][c]) : p[0][c] + times_mi(p[3][c]);
+      o.h[1][c] = FWD ? p[1][c] + times_i(p[2][c]) : p[1][c] + times_mi(p[2][c]);
+    } else if (MU == 1) {
+      o.h[0][c] = FWD ? p[0][c] + p[3][c] : p[0][c] - p[3][c];
+      o.h[1][c] = FWD ? p[1][c] - p[2][c] : p[1][c] + p[2][c];
+    } else if (MU == 2) {
+      o.h[0][c] = FWD ? p[0][c] + times_i(p[2][c]) : p[0][c] + times_mi(p[2][c]);
+      o.h[1][c] = FWD ? p[1][c] + times_mi(p[3][c]) : p[1][c] + times_i(p[3][c]);
+    } else {
+      o.h[0][c] = FWD ? p[0][c] + p[2][c] : p[0][c] - p[2][c];
+      o.h[1][c] = FWD ? p[1][c] + p[3][c] : p[1][c] - p[3][c];
+    }
+  }
+}
+
+// acc += coef * (h, lower(h)) with lower = -X^dag h (FWD) or X^dag h (BWD)
+template <int MU, bool FWD, typename T>
+__device__ inline void reconstruct(cx<T> acc[4][3], const Half2<T>& u, T coef) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<T> h0 = u.h[0][c], h1 = u.h[1][c];
+    cx<T> l0, l1;
+    if (MU == 0) {
+      l0 = times_i(h1);
+      l1 = times_i(h0);
+    } else if (MU == 1) {
+      l0 = h1;
+      l1 = neg(h0);
+    } else if (MU == 2) {
+      l0 = times_i(h0);
+      l1 = times_mi(h1);
+    } else {
+      l0 = neg(h0);
+      l1 = neg(h1);
+    }
+    if (FWD) {
+      l0 = neg(l0);
+      l1 = neg(l1);
+    }
+    acc[0][c] = acc[0][c] + coef * h0;
+    acc[1][c] = acc[1][c] + coef * h1;
+    acc[2][c] = acc[2][c] + coef * l0;
+    acc[3][c] = acc[3][c] + coef * l1;
+  }
+}
+
+template <typename Tin, typename Tc>
+__device__ inline void load_spinor(cx<Tc> p[4][3], const cx<Tin>* in, int s, size_t V, int chi_in, Tc sign) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    bool keep = chi_in < 0 || (sp >> 1) == chi_in;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cx<Tc> v = cvt<Tc>(in[(size_t)(3 * sp + c) * V + s]);
+      p[sp][c] = keep ? sign * v : mk((Tc)0, (Tc)0);
+    }
+  }
+}
+
+template <typename Tc, typename S>
+__device__ inline void load_link(cx<Tc> u[3][3], const GaugeView<S>& gv, int mu, int s, size_t V) {
+  Tc sc = (Tc)1;
+  if constexpr (is_half<S>()) sc = (Tc)gv.Usc[s];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[a][b] = sc * ldc<Tc>(gv.U, (size_t)(mu * 9 + 3 * a + b) * V + s);
+}
+
+// acc += -1/2 (1 -+ g_mu) [U_mu(slink) or U_mu(slink)^dag] p
+template <int MU, bool FWD, typename Tc, typename S>
+__device__ inline void hop_spinor(cx<Tc> acc[4][3], const cx<Tc> p[4][3], const GaugeView<S>& gv, int slink,
+                                  size_t V) {
+  Half2<Tc> h, u;
+  project<MU, FWD, Tc>(h, p);
+  cx<Tc> U[3][3];
+  load_link<Tc, S>(U, gv, MU, slink, V);
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<Tc> t = mk((Tc)0, (Tc)0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) t = FWD ? t + U[a][b] * h.h[sp][b] : t + cmulc(U[b][a], h.h[sp][b]);
+      u.h[sp][a] = t;
+    }
+  reconstruct<MU, FWD, Tc>(acc, u, (Tc)-0.5);
+}
+
+template <int MU, bool FWD, typename Tin, typename Tc, typename S>
+__device__ inline void hop(cx<Tc> acc[4][3], const cx<Tin>* in, const GaugeView<S>& gv, int sn, int slink, size_t V,
+                           int chi_in, Tc sign) {
+  cx<Tc> p[4][3];
+  load_spinor<Tin, Tc>(p, in, sn, V, chi_in, sign);
+  hop_spinor<MU, FWD, Tc, S>(acc, p, gv, slink, V);
+}
+
+// acc += A(x) psi(x) for the two chirality blocks
+template <typename Tc, typename S>
+__device__ inline void clover_apply(cx<Tc> acc[4][3], const cx<Tc> p[4][3], const GaugeView<S>& gv, int s, size_t V) {
+  Tc sc = (Tc)1;
+  if constexpr (is_half<S>()) sc = (Tc)gv.Asc[s];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const S* Ah = gv.A + (size_t)h * 36 * V;
+    cx<Tc> v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = p[2 * h + k / 3][k % 3];
+    cx<Tc> o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o[k] = (sc * ldr<Tc>(Ah, (size_t)k * V + s)) * v[k];
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) {
+        cx<Tc> a = mk(sc * ldr<Tc>(Ah, (size_t)(6 + 2 * q) * V + s), sc * ldr<Tc>(Ah, (size_t)(7 + 2 * q) * V + s));
+        o[i] = o[i] + a * v[j];
+        o[j] = o[j] + cmulc(a, v[i]);
+        ++q;
+      }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[2 * h + k / 3][k % 3] = acc[2 * h + k / 3][k % 3] + o[k];
+  }
+}
+
+template <int MU, typename Tin, typename Tc, typename S, int MODE>
+__device__ inline void hops_mu(cx<Tc> acc[4][3], const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g,
+                               const int c[4], int s, int mu_sel, int chi_in) {
+  const size_t V = g.V;
+  const int l = c[MU] % g.bs[MU];
+  bool do_f, do_b;
+  if (MODE == DS_FULL) {
+    do_f = do_b = true;
+  } else if (MODE == DS_BLOCK) {
+    do_f = l != g.bs[MU] - 1;
+    do_b = l != 0;
+  } else if (MODE == DS_CROSS_FWD) {
+    do_f = MU == mu_sel && l == g.bs[MU] - 1;
+    do_b = false;
+  } else {
+    do_f = false;
+    do_b = MU == mu_sel && l == 0;
+  }
+  if (do_f) {
+    int e[4] = {c[0], c[1], c[2], c[3]};
+    e[MU] = (c[MU] + 1 == g.L[MU]) ? 0 : c[MU] + 1;
+    Tc sign = (MU == 3 && c[3] == g.L[3] - 1) ? (Tc)-1 : (Tc)1;
+    hop<MU, true, Tin, Tc, S>(acc, in, gv, site_index(g, e), s, V, chi_in, sign);
+  }
+  if (do_b) {
+    int e[4] = {c[0], c[1], c[2], c[3]};
+    e[MU] = (c[MU] == 0) ? g.L[MU] - 1 : c[MU] - 1;
+    int sb = site_index(g, e);
+    Tc sign = (MU == 3 && c[3] == 0) ? (Tc)-1 : (Tc)1;
+    hop<MU, false, Tin, Tc, S>(acc, in, gv, sb, sb, V, chi_in, sign);
+  }
+}
+
+}  // namespace dev
+}  // namespace ddamg

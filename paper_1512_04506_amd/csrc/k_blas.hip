@@ -1,0 +1,336 @@
+// Krylov linear algebra on block vectors (one independent system per rhs):
+// several inner products in one pass (the classical Gram-Schmidt step of
+// GMRES), linear combinations, scaling, and the Arnoldi/Givens state of
+// GMRES kept on the device in FP64 (Hessenberg least squares).
+//
+// Reductions are deterministic: each workgroup writes one partial per
+// (rhs, vector, chunk) and a second kernel sums the chunks in a fixed
+// order, so repeated runs give bitwise identical results.
+#include "ddamg_internal.h"
+
+namespace ddamg {
+
+namespace {
+
+constexpr int BT = 256;
+constexpr int JG = 8;  // basis vectors per pass over the chunk
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void mdot_partial_kernel(cx<double>* part, const cx<T>* __restrict__ Vb,
+                                                          size_t vsj, size_t vsr, int nvec,
+                                                          const cx<T>* __restrict__ w, size_t wsr, size_t n,
+                                                          size_t chunk, int nchunk, const int* active) {
+  __shared__ cx<double> red[64][BT / 64];
+  const int c = blockIdx.x;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const size_t beg = (size_t)c * chunk;
+  const size_t end = min(n, beg + chunk);
+  const cx<T>* wr = w + (size_t)r * wsr;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < nvec; j0 += JG) {
+    cx<T> acc[JG];
+#pragma unroll
+    for (int q = 0; q < JG; ++q) acc[q] = mk((T)0, (T)0);
+    for (size_t i = beg + threadIdx.x; i < end; i += BT) {
+      const cx<T> wv = wr[i];
+#pragma unroll
+      for (int q = 0; q < JG; ++q)
+        if (j0 + q < nvec) acc[q] = acc[q] + cmulc(Vb[(size_t)(j0 + q) * vsj + (size_t)r * vsr + i], wv);
+    }
+#pragma unroll
+    for (int q = 0; q < JG; ++q) {
+      double re = wave_sum_d((double)acc[q].r), im = wave_sum_d((double)acc[q].i);
+      if (lane == 0 && j0 + q < nvec) red[j0 + q][wid] = mk(re, im);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nvec; j += BT) {
+    cx<double> s = mk(0.0, 0.0);
+    for (int k = 0; k < BT / 64; ++k) s = s + red[j][k];
+    part[((size_t)r * nvec + j) * nchunk + c] = s;
+  }
+}
+
+__global__ void mdot_final_kernel(cx<double>* h, int ldh, const cx<double>* part, int nvec, int nchunk,
+                                  const int* active) {
+  const int j = blockIdx.x;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  double re = 0.0, im = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += 64) {
+    cx<double> v = part[((size_t)r * nvec + j) * nchunk + c];
+    re += v.r;
+    im += v.i;
+  }
+  re = wave_sum_d(re);
+  im = wave_sum_d(im);
+  if (threadIdx.x == 0) h[(size_t)r * ldh + j] = mk(re, im);
+}
+
+template <typename Tw, typename Tv>
+__global__ __launch_bounds__(BT) void maxpy_kernel(cx<Tw>* w, size_t wsr, const cx<Tv>* __restrict__ Vb, size_t vsj,
+                                                   size_t vsr, int nvec, const cx<double>* __restrict__ h, int ldh,
+                                                   double sign, size_t n, const int* active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  using Tc = typename std::conditional<(sizeof(Tw) > sizeof(Tv)), Tw, Tv>::type;
+  const cx<double>* hr = h + (size_t)r * ldh;
+  for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < n; i += (size_t)gridDim.x * BT) {
+    cx<Tc> acc = cvt<Tc>(w[(size_t)r * wsr + i]);
+    for (int j = 0; j < nvec; ++j)
+      acc = acc + cvt<Tc>(sign * hr[j]) * cvt<Tc>(Vb[(size_t)j * vsj + (size_t)r * vsr + i]);
+    w[(size_t)r * wsr + i] = cvt<Tw>(acc);
+  }
+}
+
+template <typename Ty, typename Tx>
+__global__ __launch_bounds__(BT) void scale_kernel(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr,
+                                                   const double* s, size_t n, const int* active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const double f = s[r];
+  for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < n; i += (size_t)gridDim.x * BT) {
+    cx<double> v = cvt<double>(x[(size_t)r * xstr + i]);
+    y[(size_t)r * ystr + i] = cvt<Ty>(f * v);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void sub_kernel(cx<T>* y, size_t ystr, const cx<T>* a, size_t astr, const cx<T>* b,
+                                                 size_t bstr, size_t n) {
+  const int r = blockIdx.y;
+  for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < n; i += (size_t)gridDim.x * BT)
+    y[(size_t)r * ystr + i] = a[(size_t)r * astr + i] - b[(size_t)r * bstr + i];
+}
+
+template <typename Ty, typename Tx>
+__global__ __launch_bounds__(BT) void copy_kernel(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, size_t n) {
+  const int r = blockIdx.y;
+  for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < n; i += (size_t)gridDim.x * BT)
+    y[(size_t)r * ystr + i] = cvt<Ty>(x[(size_t)r * xstr + i]);
+}
+
+inline unsigned grid_for(size_t n) {
+  size_t b = (n + BT - 1) / BT;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// ----------------------------------------------------- Arnoldi / Givens
+__device__ inline double cabs2(cx<double> a) { return a.r * a.r + a.i * a.i; }
+
+// rotation [c s; -conj(s) c] (c real) with c a + s b = r, -conj(s) a + c b = 0
+__device__ inline void givens(cx<double> a, cx<double> b, double& c, cx<double>& s, cx<double>& r) {
+  const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
+  if (nb == 0.0) {
+    c = 1.0;
+    s = mk(0.0, 0.0);
+    r = a;
+    return;
+  }
+  if (na == 0.0) {
+    c = 0.0;
+    s = (1.0 / nb) * conj(b);
+    r = mk(nb, 0.0);
+    return;
+  }
+  const double nrm = sqrt(na * na + nb * nb);
+  const cx<double> ph = (1.0 / na) * a;
+  c = na / nrm;
+  s = (1.0 / nrm) * (ph * conj(b));
+  r = nrm * ph;
+}
+
+__global__ void arnoldi_start_kernel(ArnoldiState s, const cx<double>* norm2, int ldn, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const int m = s.m;
+  const double beta = sqrt(fmax(norm2[(size_t)r * ldn].r, 0.0));
+  for (int j = 0; j <= m; ++j) s.g[(size_t)r * (m + 1) + j] = mk(0.0, 0.0);
+  s.g[(size_t)r * (m + 1)] = mk(beta, 0.0);
+  const double tol = s.abstol[r];
+  const bool act = tol < 0.0 ? beta > 0.0 : beta > tol;
+  s.active[r] = act ? 1 : 0;
+  s.inv_h[r] = act ? 1.0 / beta : 0.0;
+  s.kdone[r] = 0;
+  s.est[r] = beta;
+}
+
+__global__ void arnoldi_column_kernel(ArnoldiState s, int k, const cx<double>* h1, const cx<double>* h2, int ldh,
+                                      const cx<double>* norm2, int ldn, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  if (!s.active[r]) {
+    s.inv_h[r] = 0.0;
+    return;
+  }
+  const int m = s.m;
+  cx<double>* H = s.H + (size_t)r * (m + 1) * m + (size_t)k * (m + 1);
+  cx<double>* cs = s.cs + (size_t)r * m;
+  cx<double>* sn = s.sn + (size_t)r * m;
+  cx<double>* g = s.g + (size_t)r * (m + 1);
+  for (int j = 0; j <= k; ++j) {
+    cx<double> v = h1[(size_t)r * ldh + j];
+    if (h2) v = v + h2[(size_t)r * ldh + j];
+    H[j] = v;
+  }
+  const double hn = sqrt(fmax(norm2[(size_t)r * ldn].r, 0.0));
+  H[k + 1] = mk(hn, 0.0);
+  for (int j = 0; j < k; ++j) {
+    const double c = cs[j].r;
+    const cx<double> sj = sn[j];
+    const cx<double> t = c * H[j] + sj * H[j + 1];
+    H[j + 1] = c * H[j + 1] - conj(sj) * H[j];
+    H[j] = t;
+  }
+  double c;
+  cx<double> sv, rr;
+  givens(H[k], H[k + 1], c, sv, rr);
+  cs[k] = mk(c, 0.0);
+  sn[k] = sv;
+  H[k] = rr;
+  H[k + 1] = mk(0.0, 0.0);
+  const cx<double> gk = g[k];
+  g[k + 1] = neg(conj(sv) * gk);
+  g[k] = c * gk;
+  const double est = sqrt(cabs2(g[k + 1]));
+  s.est[r] = est;
+  s.kdone[r] = k + 1;
+  const double tol = s.abstol[r];
+  const bool stop = !(hn > 0.0) || (tol >= 0.0 && est <= tol) || k + 1 >= m;
+  s.active[r] = stop ? 0 : 1;
+  s.inv_h[r] = stop ? 0.0 : 1.0 / hn;
+}
+
+__global__ void arnoldi_solve_kernel(ArnoldiState s, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const int m = s.m;
+  const int kd = s.kdone[r];
+  const cx<double>* H = s.H + (size_t)r * (m + 1) * m;
+  const cx<double>* g = s.g + (size_t)r * (m + 1);
+  cx<double>* y = s.y + (size_t)r * m;
+  for (int j = kd; j < m; ++j) y[j] = mk(0.0, 0.0);
+  for (int i = kd - 1; i >= 0; --i) {
+    cx<double> v = g[i];
+    for (int j = i + 1; j < kd; ++j) v = v - H[(size_t)j * (m + 1) + i] * y[j];
+    const cx<double> d = H[(size_t)i * (m + 1) + i];
+    const double dn = cabs2(d);
+    y[i] = dn > 0.0 ? (1.0 / dn) * (conj(d) * v) : mk(0.0, 0.0);
+  }
+}
+
+// abstol[r] = tol * sqrt(|n2[r]|) (tol < 0: -1, i.e. never test)
+__global__ void set_abstol_kernel(double* abstol, const cx<double>* n2, double tol, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  abstol[r] = tol < 0.0 ? -1.0 : tol * sqrt(fmax(n2[r].r, 0.0));
+}
+
+// s[r] = 1 / sqrt(n2[r]); flags a zero or non-finite norm in *status
+__global__ void inv_norm_kernel(double* s, const cx<double>* n2, int nrhs, int* status) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const double nr = sqrt(fmax(n2[r].r, 0.0));
+  if (!(nr > 0.0) || !isfinite(nr)) {
+    atomicExch(status, 1);
+    s[r] = 0.0;
+  } else {
+    s[r] = 1.0 / nr;
+  }
+}
+
+}  // namespace
+
+void launch_set_abstol(double* abstol, const cx<double>* n2, double tol, int nrhs, hipStream_t st) {
+  set_abstol_kernel<<<1, 64, 0, st>>>(abstol, n2, tol, nrhs);
+}
+void launch_inv_norm(double* s, const cx<double>* n2, int nrhs, int* status, hipStream_t st) {
+  inv_norm_kernel<<<1, 64, 0, st>>>(s, n2, nrhs, status);
+}
+
+int blas_nchunks(size_t n) {
+  size_t c = (n + 8191) / 8192;
+  if (c < 1) c = 1;
+  if (c > 512) c = 512;
+  return (int)c;
+}
+
+template <typename T>
+void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size_t vsj, size_t vsr, int nvec,
+                 const cx<T>* w, size_t wsr, size_t n, int nrhs, const int* active, hipStream_t st) {
+  if (nrhs <= 0 || nvec <= 0) return;
+  const int nchunk = blas_nchunks(n);
+  const size_t chunk = (n + nchunk - 1) / nchunk;
+  mdot_partial_kernel<T><<<dim3(nchunk, nrhs), BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, n, chunk, nchunk,
+                                                            active);
+  mdot_final_kernel<<<dim3(nvec, nrhs), 64, 0, st>>>(h, ldh, part, nvec, nchunk, active);
+}
+
+template <typename Tw, typename Tv>
+void launch_maxpy(cx<Tw>* w, size_t wsr, const cx<Tv>* Vb, size_t vsj, size_t vsr, int nvec, const cx<double>* h,
+                  int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st) {
+  if (nrhs <= 0 || nvec <= 0) return;
+  maxpy_kernel<Tw, Tv><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(w, wsr, Vb, vsj, vsr, nvec, h, ldh, sign, n, active);
+}
+
+template <typename Ty, typename Tx>
+void launch_scale(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, const double* s, size_t n, int nrhs,
+                  const int* active, hipStream_t st) {
+  if (nrhs <= 0) return;
+  scale_kernel<Ty, Tx><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(y, ystr, x, xstr, s, n, active);
+}
+
+template <typename T>
+void launch_sub(cx<T>* y, size_t ystr, const cx<T>* a, size_t astr, const cx<T>* b, size_t bstr, size_t n, int nrhs,
+                hipStream_t st) {
+  if (nrhs <= 0) return;
+  sub_kernel<T><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(y, ystr, a, astr, b, bstr, n);
+}
+
+template <typename Ty, typename Tx>
+void launch_copy(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, size_t n, int nrhs, hipStream_t st) {
+  if (nrhs <= 0) return;
+  copy_kernel<Ty, Tx><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(y, ystr, x, xstr, n);
+}
+
+void launch_arnoldi_start(ArnoldiState s, const cx<double>* norm2, int ldn, int nrhs, hipStream_t st) {
+  arnoldi_start_kernel<<<1, 64, 0, st>>>(s, norm2, ldn, nrhs);
+}
+void launch_arnoldi_column(ArnoldiState s, int k, const cx<double>* h1, const cx<double>* h2, int ldh,
+                           const cx<double>* norm2, int ldn, int nrhs, hipStream_t st) {
+  arnoldi_column_kernel<<<1, 64, 0, st>>>(s, k, h1, h2, ldh, norm2, ldn, nrhs);
+}
+void launch_arnoldi_solve(ArnoldiState s, int nrhs, hipStream_t st) {
+  arnoldi_solve_kernel<<<1, 64, 0, st>>>(s, nrhs);
+}
+
+template void launch_mdot<double>(cx<double>*, int, cx<double>*, const cx<double>*, size_t, size_t, int,
+                                  const cx<double>*, size_t, size_t, int, const int*, hipStream_t);
+template void launch_mdot<float>(cx<double>*, int, cx<double>*, const cx<float>*, size_t, size_t, int,
+                                 const cx<float>*, size_t, size_t, int, const int*, hipStream_t);
+#define INST2(A, B)                                                                                                   \
+  template void launch_maxpy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, const cx<double>*, int, double, \
+                                   size_t, int, const int*, hipStream_t);                                             \
+  template void launch_scale<A, B>(cx<A>*, size_t, const cx<B>*, size_t, const double*, size_t, int, const int*,      \
+                                   hipStream_t);                                                                      \
+  template void launch_copy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, hipStream_t);
+INST2(double, double)
+INST2(float, float)
+INST2(double, float)
+INST2(float, double)
+#undef INST2
+template void launch_sub<double>(cx<double>*, size_t, const cx<double>*, size_t, const cx<double>*, size_t, size_t, int,
+                                 hipStream_t);
+template void launch_sub<float>(cx<float>*, size_t, const cx<float>*, size_t, const cx<float>*, size_t, size_t, int,
+                                hipStream_t);
+
+}  // namespace ddamg

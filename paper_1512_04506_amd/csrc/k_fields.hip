@@ -1,0 +1,260 @@
+// Field preparation kernels: gauge import, clover term, storage
+// quantisation and canonical <-> internal spinor layouts.
+#include "ddamg_internal.h"
+
+namespace ddamg {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblk(size_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+__global__ void gauge_import_kernel(cx<double>* U, const cx<double>* canon, int V) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int e = 0; e < 9; ++e) U[((size_t)mu * 9 + e) * V + s] = canon[((size_t)s * 4 + mu) * 9 + e];
+}
+
+struct M3 {
+  cx<double> a[3][3];
+};
+
+__device__ inline M3 load_link(const cx<double>* U, int V, int mu, int s) {
+  M3 m;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) m.a[i][j] = U[((size_t)mu * 9 + 3 * i + j) * V + s];
+  return m;
+}
+__device__ inline M3 mul(const M3& x, const M3& y) {
+  M3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cx<double> acc = mk(0.0, 0.0);
+      for (int k = 0; k < 3; ++k) acc = acc + x.a[i][k] * y.a[k][j];
+      r.a[i][j] = acc;
+    }
+  return r;
+}
+__device__ inline M3 dag(const M3& x) {
+  M3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r.a[i][j] = conj(x.a[j][i]);
+  return r;
+}
+__device__ inline int nb(const Geom& g, const int c[4], int mu, int d) {
+  int e[4] = {c[0], c[1], c[2], c[3]};
+  e[mu] = (e[mu] + d + g.L[mu]) % g.L[mu];
+  return site_index(g, e);
+}
+__device__ inline int nb2(const Geom& g, const int c[4], int mu, int dmu, int nu, int dnu) {
+  int e[4] = {c[0], c[1], c[2], c[3]};
+  e[mu] = (e[mu] + dmu + g.L[mu]) % g.L[mu];
+  e[nu] = (e[nu] + dnu + g.L[nu]) % g.L[nu];
+  return site_index(g, e);
+}
+
+// F_{mu nu}(x) = (Q - Q^dag) / 8 with Q the sum of the four plaquette leaves
+// at x in the (mu, nu) plane, all traversed in the same sense.
+__device__ M3 field_strength(const cx<double>* U, const Geom& g, const int c[4], int s, int mu, int nu) {
+  const int V = g.V;
+  int xpm = nb(g, c, mu, +1), xpn = nb(g, c, nu, +1);
+  int xmm = nb(g, c, mu, -1), xmn = nb(g, c, nu, -1);
+  int xmm_pn = nb2(g, c, mu, -1, nu, +1);
+  int xmm_mn = nb2(g, c, mu, -1, nu, -1);
+  int xpm_mn = nb2(g, c, mu, +1, nu, -1);
+  M3 Umu = load_link(U, V, mu, s), Unu = load_link(U, V, nu, s);
+  // x -> x+mu -> x+mu+nu -> x+nu -> x
+  M3 q1 = mul(mul(Umu, load_link(U, V, nu, xpm)), mul(dag(load_link(U, V, mu, xpn)), dag(Unu)));
+  // x -> x+nu -> x-mu+nu -> x-mu -> x
+  M3 q2 = mul(mul(Unu, dag(load_link(U, V, mu, xmm_pn))), mul(dag(load_link(U, V, nu, xmm)), load_link(U, V, mu, xmm)));
+  // x -> x-mu -> x-mu-nu -> x-nu -> x
+  M3 q3 = mul(mul(dag(load_link(U, V, mu, xmm)), dag(load_link(U, V, nu, xmm_mn))),
+              mul(load_link(U, V, mu, xmm_mn), load_link(U, V, nu, xmn)));
+  // x -> x-nu -> x+mu-nu -> x+mu -> x
+  M3 q4 = mul(mul(dag(load_link(U, V, nu, xmn)), load_link(U, V, mu, xmn)), mul(load_link(U, V, nu, xpm_mn), dag(Umu)));
+  M3 F;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cx<double> q = q1.a[i][j] + q2.a[i][j] + q3.a[i][j] + q4.a[i][j];
+      cx<double> qd = conj(q1.a[j][i] + q2.a[j][i] + q3.a[j][i] + q4.a[j][i]);
+      F.a[i][j] = 0.125 * (q - qd);
+    }
+  return F;
+}
+
+// Packing of one 6x6 Hermitian chirality block into 36 reals.
+__device__ inline int upper_index(int i, int j) {  // i < j
+  // number of pairs before row i: sum_{k<i} (5 - k)
+  return i * 5 - (i * (i - 1)) / 2 + (j - i - 1);
+}
+
+// In the chiral basis sigma_{mu nu} is block diagonal.  With Pauli matrices
+// s_l and planes written 0-based (x, y, z, t):
+//   left  block: sum_{mu<nu} sigma F = s1 B1 + s2 B2 + s3 B3 with
+//       B1 = -(F12 + F03), B2 = F02 - F13, B3 = -(F01 + F23)
+//   right block: B1 = F03 - F12, B2 = F02 + F13, B3 = F23 - F01
+// (sigma_{k4} = diag(-s_k, s_k), sigma_{jk} = -eps_{jkl} diag(s_l, s_l)),
+// and A^h = (4 + m0) + c_sw (i/2) sum_l s_l (x) B_l.
+__global__ void clover_kernel(double* A, const cx<double>* U, Geom g, double m0, double csw) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  int c[4];
+  site_coords(g, s, c);
+  M3 F01 = field_strength(U, g, c, s, 0, 1);
+  M3 F02 = field_strength(U, g, c, s, 0, 2);
+  M3 F12 = field_strength(U, g, c, s, 1, 2);
+  M3 F03 = field_strength(U, g, c, s, 0, 3);
+  M3 F13 = field_strength(U, g, c, s, 1, 3);
+  M3 F23 = field_strength(U, g, c, s, 2, 3);
+  const size_t V = g.V;
+  for (int h = 0; h < 2; ++h) {
+    M3 B1, B2, B3;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        if (h == 0) {
+          B1.a[i][j] = neg(F12.a[i][j] + F03.a[i][j]);
+          B2.a[i][j] = F02.a[i][j] - F13.a[i][j];
+          B3.a[i][j] = neg(F01.a[i][j] + F23.a[i][j]);
+        } else {
+          B1.a[i][j] = F03.a[i][j] - F12.a[i][j];
+          B2.a[i][j] = F02.a[i][j] + F13.a[i][j];
+          B3.a[i][j] = F23.a[i][j] - F01.a[i][j];
+        }
+      }
+    // spin blocks of M = sum s_l B_l: [[B3, B1 - i B2], [B1 + i B2, -B3]]
+    cx<double> full[6][6];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        cx<double> m00 = B3.a[i][j];
+        cx<double> m01 = B1.a[i][j] + times_mi(B2.a[i][j]);
+        cx<double> m10 = B1.a[i][j] + times_i(B2.a[i][j]);
+        cx<double> m11 = neg(B3.a[i][j]);
+        double f = 0.5 * csw;
+        full[i][j] = f * times_i(m00);
+        full[i][3 + j] = f * times_i(m01);
+        full[3 + i][j] = f * times_i(m10);
+        full[3 + i][3 + j] = f * times_i(m11);
+      }
+    double* Ah = A + (size_t)h * 36 * V;
+    for (int k = 0; k < 6; ++k) Ah[(size_t)k * V + s] = 4.0 + m0 + full[k][k].r;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int p = upper_index(i, j);
+        Ah[(size_t)(6 + 2 * p) * V + s] = full[i][j].r;
+        Ah[(size_t)(7 + 2 * p) * V + s] = full[i][j].i;
+      }
+  }
+}
+
+template <typename S>
+__global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, S* Aq, float* Asc, const cx<double>* U,
+                                      const double* A, int V) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  if constexpr (is_half<S>()) {
+    double mu = 0.0, ma = 0.0;
+    for (int e = 0; e < 36; ++e) {
+      cx<double> u = U[(size_t)e * V + s];
+      mu = fmax(mu, fmax(fabs(u.r), fabs(u.i)));
+    }
+    for (int e = 0; e < 72; ++e) ma = fmax(ma, fabs(A[(size_t)e * V + s]));
+    float fu = (float)mu, fa = (float)ma;
+    double iu = fu > 0.f ? 1.0 / (double)fu : 0.0, ia = fa > 0.f ? 1.0 / (double)fa : 0.0;
+    Usc[s] = fu;
+    Asc[s] = fa;
+    for (int e = 0; e < 36; ++e) {
+      cx<double> u = U[(size_t)e * V + s];
+      Uq[(size_t)e * V + s] = __floats2half2_rn((float)(u.r * iu), (float)(u.i * iu));
+    }
+    for (int e = 0; e < 72; ++e) Aq[(size_t)e * V + s] = __float2half_rn((float)(A[(size_t)e * V + s] * ia));
+  } else {
+    for (int e = 0; e < 36; ++e) stc_store(Uq, (size_t)e * V + s, U[(size_t)e * V + s]);
+    for (int e = 0; e < 72; ++e) Aq[(size_t)e * V + s] = (S)A[(size_t)e * V + s];
+  }
+}
+
+template <typename T>
+__global__ void spinor_to_internal_kernel(cx<T>* out, const cx<double>* canon, int V, int nrhs) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)nrhs * 12 * V;
+  if (idx >= n) return;
+  int s = (int)(idx % V);
+  size_t rc = idx / V;
+  int comp = (int)(rc % 12);
+  int r = (int)(rc / 12);
+  out[idx] = cvt<T>(canon[((size_t)r * V + s) * 12 + comp]);
+}
+
+template <typename T>
+__global__ void spinor_to_canonical_kernel(cx<double>* canon, const cx<T>* in, int V, int nrhs) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)nrhs * 12 * V;
+  if (idx >= n) return;
+  int s = (int)(idx % V);
+  size_t rc = idx / V;
+  int comp = (int)(rc % 12);
+  int r = (int)(rc / 12);
+  canon[((size_t)r * V + s) * 12 + comp] = cvt<double>(in[idx]);
+}
+
+__global__ void clover_export_kernel(cx<double>* out, const double* A, int V) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  for (int h = 0; h < 2; ++h) {
+    const double* Ah = A + (size_t)h * 36 * V;
+    cx<double>* o = out + ((size_t)s * 2 + h) * 36;
+    for (int k = 0; k < 6; ++k) o[k * 6 + k] = mk(Ah[(size_t)k * V + s], 0.0);
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int p = upper_index(i, j);
+        cx<double> v = mk(Ah[(size_t)(6 + 2 * p) * V + s], Ah[(size_t)(7 + 2 * p) * V + s]);
+        o[i * 6 + j] = v;
+        o[j * 6 + i] = conj(v);
+      }
+  }
+}
+
+}  // namespace
+
+void launch_gauge_import(cx<double>* U, const cx<double>* canon, const Geom& g, hipStream_t st) {
+  gauge_import_kernel<<<nblk(g.V), TPB, 0, st>>>(U, canon, g.V);
+}
+
+void launch_clover_build(double* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st) {
+  clover_kernel<<<nblk(g.V, 128), 128, 0, st>>>(A, U, g, m0, csw);
+}
+
+template <typename S>
+void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, S* Aq, float* Asc, const cx<double>* U, const double* A,
+                           const Geom& g, hipStream_t st) {
+  quantize_gauge_kernel<S><<<nblk(g.V), TPB, 0, st>>>(Uq, Usc, Aq, Asc, U, A, g.V);
+}
+template void launch_quantize_gauge<double>(stc_t<double>*, float*, double*, float*, const cx<double>*,
+                                            const double*, const Geom&, hipStream_t);
+template void launch_quantize_gauge<float>(stc_t<float>*, float*, float*, float*, const cx<double>*, const double*,
+                                           const Geom&, hipStream_t);
+template void launch_quantize_gauge<__half>(stc_t<__half>*, float*, __half*, float*, const cx<double>*,
+                                            const double*, const Geom&, hipStream_t);
+
+template <typename T>
+void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
+  size_t n = (size_t)nrhs * 12 * g.V;
+  if (n) spinor_to_internal_kernel<T><<<nblk(n), TPB, 0, st>>>(out, canon, g.V, nrhs);
+}
+template <typename T>
+void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st) {
+  size_t n = (size_t)nrhs * 12 * g.V;
+  if (n) spinor_to_canonical_kernel<T><<<nblk(n), TPB, 0, st>>>(canon, in, g.V, nrhs);
+}
+template void launch_spinor_to_internal<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
+template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, const Geom&, int, hipStream_t);
+template void launch_spinor_to_canonical<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
+template void launch_spinor_to_canonical<float>(cx<double>*, const cx<float>*, const Geom&, int, hipStream_t);
+
+void launch_clover_export(cx<double>* out, const double* A, const Geom& g, hipStream_t st) {
+  clover_export_kernel<<<nblk(g.V), TPB, 0, st>>>(out, A, g.V);
+}
+
+}  // namespace ddamg

@@ -1,0 +1,258 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances (relative, max-norm over the whole output unless stated):
+operator applies 1e-12 in FP64, 1e-5 in FP32, 1e-2 with 16-bit storage;
+composite V-cycle in deterministic mode (fixed coarse iterations) 1e-10 in
+FP64; every solution reaches ||f - D u|| / ||f|| <= 1e-10 recomputed by the
+oracle's own D.  Lattices are chosen to span several 256-thread tiles with
+a ragged tail (V not a multiple of 256, block volumes not multiples of 64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, sap, coarse, mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1512_04506_amd as dd
+    return dd
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CASES = {
+    # name: L, block, eps, m0, ntv
+    "c1_4x4x4x4": ((4, 4, 4, 4), (2, 2, 2, 2), 0.3, -0.1, 8),
+    "ragged_6x4x4x4": ((6, 4, 4, 4), (3, 2, 2, 2), 0.5, -0.2, 6),
+    "tiles_8x8x4x8": ((8, 8, 4, 8), (4, 4, 2, 4), 0.5, -0.2, 12),
+}
+TOL = {0: 1e-12, 1: 1e-5, 2: 1e-2}
+
+
+def make_ctx(dd, L, block, eps, m0, ntv, prec, seed=7, **kw):
+    U = synth.su3_field(L, eps, seed)
+    p = dd.default_params(L=L, block=block, m0=m0, csw=1.0, ntv=ntv, prec=prec, max_rhs=kw.pop("max_rhs", 4), **kw)
+    ctx = dd.Context(p, dev(U))
+    return ctx, U
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_dirac_apply(case, prec):
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES[case]
+    say("dirac_apply", case, "prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    A = dirac.clover_term(U, m0, 1.0)
+    psi = synth.gaussian_spinors(L, 3, 11)
+    out = torch.zeros_like(dev(psi))
+    ctx.dirac_apply(out, dev(psi), 3, prec)
+    got = host(out)
+    ref = np.stack([dirac.apply_D(U, A, psi[r]) for r in range(3)])
+    assert rel(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_clover_export(case):
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES[case]
+    say("clover", case)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 0)
+    V = int(np.prod(L))
+    out = torch.zeros((V, 2, 6, 6), dtype=torch.complex128, device="cuda")
+    ctx.export_clover(out)
+    A = dirac.clover_term(U, m0, 1.0).reshape(V, 12, 12)
+    ref = np.stack([A[:, :6, :6], A[:, 6:, 6:]], axis=1)
+    assert rel(host(out), ref) <= 1e-13
+
+
+def _basis(L, block, ntv, seed=21):
+    blk = sap.Blocking(L, block)
+    W = coarse.orthonormalise(blk, synth.gaussian_spinors(L, ntv, seed))
+    return blk, W
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_coarse_operator_restrict_prolong(case, prec):
+    """Imported orthonormal basis: D_c (Eq. cgo, backward slots from
+    Eq. dagger on the GPU, computed directly by the oracle), R y, P x_c and
+    the stencil apply all match the oracle."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES[case]
+    say("coarse operator", case, "prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    A = dirac.clover_term(U, m0, 1.0)
+    blk, W = _basis(L, block, ntv)
+    ctx.import_basis(dev(W))
+    nb, n = blk.nblocks, 2 * ntv
+    Dc_ref = coarse.coarse_operator(U, A, blk, W)
+    Dc = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
+    ctx.export_coarse(Dc)
+    assert rel(host(Dc), Dc_ref) <= TOL[prec]
+    # R y and P x_c
+    y = synth.gaussian_spinors(L, 2, 31)
+    yc = torch.zeros((2, nb, 2, ntv), dtype=torch.complex128, device="cuda")
+    ctx.mg_restrict(yc, dev(y), 2)
+    assert rel(host(yc), coarse.restrict(blk, W, y)) <= TOL[prec]
+    xc = synth.gaussian_coarse(nb, ntv, 2, 32)
+    x = torch.zeros_like(dev(y))
+    ctx.mg_prolong(x, dev(xc), 2)
+    assert rel(host(x), coarse.prolong(blk, W, xc)) <= TOL[prec]
+    # stencil apply
+    out = torch.zeros_like(dev(xc))
+    ctx.coarse_apply(out, dev(xc), 2)
+    nbr = coarse.neighbour_table(blk)
+    ref = coarse.coarse_apply(Dc_ref, nbr, xc.reshape(2, nb, n)).reshape(xc.shape)
+    assert rel(host(out), ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("case", ["c1_4x4x4x4", "ragged_6x4x4x4"])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_vcycle_deterministic(case, prec):
+    """Alg. 1 with a fixed number of coarse GMRES iterations (no tolerance
+    test), imported basis: GPU V-cycle == oracle V-cycle."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES[case]
+    say("vcycle", case, "prec", prec)
+    its = 7
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, coarse_fixed_its=its, coarse_restart=5)
+    blk, W = _basis(L, block, ntv)
+    ctx.import_basis(dev(W))
+    p = mg.Params(L, block, m0, 1.0, ntv, coarse_fixed_its=its, coarse_restart=5)
+    M = mg.MG(p, U)
+    M.set_basis(W)
+    y = synth.gaussian_spinors(L, 2, 41)
+    x = torch.zeros_like(dev(y))
+    ctx.mg_apply(x, dev(y), 2)
+    ref = np.stack([M.vcycle(y[r]) for r in range(2)])
+    tol = {0: 1e-10, 1: 1e-5, 2: 2e-2}[prec]
+    assert rel(host(x), ref) <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_setup_deterministic(prec):
+    """Alg. 4/5 end to end from the same random start vectors with fixed
+    coarse iterations: the GPU aggregate basis and D_c match the oracle's."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    say("setup", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, coarse_fixed_its=6, coarse_restart=30, n_setup=2)
+    tv = synth.gaussian_spinors(L, ntv, 102)
+    ctx.mg_setup(dev(tv))
+    p = mg.Params(L, block, m0, 1.0, ntv, coarse_fixed_its=6, n_setup=2)
+    M = mg.MG(p, U)
+    M.setup(tv)
+    W = torch.zeros_like(dev(tv))
+    ctx.export_basis(W)
+    tol = {0: 1e-9, 1: 1e-4, 2: 5e-2}[prec]
+    assert rel(host(W), M.W) <= tol
+    nb, n = M.blk.nblocks, 2 * ntv
+    Dc = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
+    ctx.export_coarse(Dc)
+    assert rel(host(Dc), M.Dc) <= tol
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_solve_residual(case, prec):
+    """Every solution reaches 1e-10 relative residual, recomputed by the
+    oracle's own FP64 D; it agrees with the oracle's solve."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES[case]
+    say("solve", case, "prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, max_rhs=ntv)
+    tv = synth.gaussian_spinors(L, ntv, 102)
+    ctx.mg_setup(dev(tv))
+    A = dirac.clover_term(U, m0, 1.0)
+    f = synth.gaussian_spinors(L, 3, 103)
+    u = torch.zeros_like(dev(f))
+    rc, st = ctx.solve(u, dev(f), 3, 1e-10)
+    assert rc == 0, st
+    uh = host(u)
+    for r in range(3):
+        res = f[r] - dirac.apply_D(U, A, uh[r])
+        assert np.linalg.norm(res) / np.linalg.norm(f[r]) <= 1e-10
+        assert st["relres"][r] <= 1e-10
+    if case == "c1_4x4x4x4":
+        p = mg.Params(L, block, m0, 1.0, ntv)
+        M = mg.MG(p, U)
+        M.setup(tv)
+        uo, _ = M.solve(f[0])
+        assert rel(uh[0], uo) <= 1e-8
+
+
+def test_solve_batching_invariance():
+    """rhs k solved alone equals rhs k solved in a batch (independent Krylov
+    per rhs, shared launches), up to the solver tolerance."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["ragged_6x4x4x4"]
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 1, max_rhs=ntv)
+    ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 5)))
+    f = synth.gaussian_spinors(L, 3, 6)
+    u = torch.zeros_like(dev(f))
+    ctx.solve(u, dev(f), 3, 1e-10)
+    u1 = torch.zeros_like(dev(f[1:2]))
+    ctx.solve(u1, dev(f[1:2].copy()), 1, 1e-10)
+    assert rel(host(u)[1], host(u1)[0]) <= 1e-8
+
+
+def test_solve_zero_and_point_sources():
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 2, max_rhs=12)
+    ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 8)))
+    f = synth.point_sources(L)
+    f[3] = 0.0
+    u = torch.ones_like(dev(f))
+    rc, st = ctx.solve(u, dev(f), 12, 1e-10)
+    assert rc == 0
+    uh = host(u)
+    assert np.all(uh[3] == 0)
+    A = dirac.clover_term(U, m0, 1.0)
+    for r in range(12):
+        if r == 3:
+            continue
+        res = f[r] - dirac.apply_D(U, A, uh[r])
+        assert np.linalg.norm(res) / np.linalg.norm(f[r]) <= 1e-10
+
+
+def test_errors_before_setup_and_bad_args():
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 0)
+    y = dev(synth.gaussian_spinors(L, 1, 1))
+    x = torch.zeros_like(y)
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.mg_apply(x, y, 1)
+    assert e.value.code == -2
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.dirac_apply(x, y, 1, prec=7)
+    assert e.value.code == -1
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.dirac_apply(y, y, 1)
+    assert e.value.code == -1

@@ -31,6 +31,8 @@ WORKLOADS = {
                seeds=(101, 102), name="4^4 eps0.3 m0-0.1 csw1 blocks2^4 Ntv8 1 gaussian rhs"),
 }
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32
+FP64_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -59,6 +61,8 @@ def run_path(dd, torch, w, prec, U_d, tv_d, f_d, steps, warmup):
     res = {"setup_ms": [], "solve_ms": [], "step_ms": []}
     st = None
     for it in range(warmup + steps):
+        if it == warmup:
+            ctx.set_kernel_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.mg_setup(tv_d)
@@ -76,6 +80,8 @@ def run_path(dd, torch, w, prec, U_d, tv_d, f_d, steps, warmup):
             res["step_ms"].append((t2 - t0) * 1e3)
         log("  prec %d step %d: setup %.1f ms solve %.1f ms outer its %d coarse its max %d" %
             (prec, it, (t1 - t0) * 1e3, (t2 - t1) * 1e3, st["outer_iterations"], st["coarse_iterations_max"]))
+    res["kernel_times"] = ctx.kernel_times()
+    ctx.set_kernel_timing(False)
     res["stats"] = st
     res["ctx"] = ctx
     res["u"] = u
@@ -122,6 +128,57 @@ def kernel_rooflines(dd, torch, ctx, w, reps=50):
         ms = time_kernel(torch, lambda: ctx.coarse_apply_internal(y, x, nr), reps)
         by = nb * (9 * nc * nc * 4 + 9 * 4 + nr * 2 * nc * 8)
         out["coarse_mixed16_%drhs" % nr] = dict(ms=ms, bytes=by, gbs=by / ms / 1e6)
+    return out
+
+
+def sap_flops_per_site(block, n_mr):
+    """Algorithmic flops of one SAP colour phase per site of that colour and
+    rhs: residual y - D x (1320 hop + 504 clover + 24), n_mr MR steps each
+    with B rho (clover 504 + the in-block share of the 1320 hop flops) and
+    two inner products and two axpys (336), and the update x += e (24)."""
+    inblock = sum((b - 1) / b for b in block) / 4.0
+    return 1320 + 504 + 24 + n_mr * (504 + 1320 * inblock + 336) + 24
+
+
+def dominant_roofline(w, kt, prec):
+    """Roofline record of the kernel class with the largest total time in
+    the timed steps, from the library's per-launch HIP events.  Algorithmic
+    work per class (each datum counted once per launch):
+      sap      flops: rhs x V/2 x sap_flops_per_site      (FP32 ALU bound)
+      dslash   bytes: launches x V x 1152 (FP64 links + clover)
+                      + rhs x V x (12 x 8 in + 12 x 16 out)  (HBM bound)
+      restrict / prolong bytes: launches x V x ntv x (12 x w + s)
+                      + rhs x V x 12 x 8   (w = 4, s = 4 for FP16 + scale)
+    Other classes are reported in kernel_times only."""
+    V = 1
+    for x in w["L"]:
+        V *= x
+    ntv = w["ntv"]
+    sb = 8 if prec != 0 else 16
+    wb, ws = (4, 4) if prec == 2 else ((8, 0) if prec == 1 else (16, 0))
+    cand = {}
+    for kind, (ms, cnt, rhs) in kt.items():
+        if cnt == 0 or ms <= 0:
+            continue
+        if kind == "sap":
+            work = rhs * (V / 2) * sap_flops_per_site(w["block"], 4)
+            cand[kind] = dict(bound="alu", achieved=work / (ms * 1e-3) / 1e12,
+                              peak=FP32_PEAK_TFLOPS if prec != 0 else FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                              per_launch=work / cnt, ms=ms, launches=cnt)
+        elif kind == "dslash":
+            work = cnt * V * 1152 + rhs * V * (12 * sb + 192)
+            cand[kind] = dict(bound="hbm", achieved=work / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                              per_launch=work / cnt, ms=ms, launches=cnt)
+        elif kind in ("restrict", "prolong"):
+            work = cnt * V * ntv * (12 * wb + ws) + rhs * V * 12 * sb
+            cand[kind] = dict(bound="hbm", achieved=work / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                              per_launch=work / cnt, ms=ms, launches=cnt)
+    kind = max(cand, key=lambda k: cand[k]["ms"])
+    r = cand[kind]
+    out = {"bound": r["bound"], "kernel": kind, "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
+           "frac": r["achieved"] / r["peak"], "traffic": None,
+           "avg_launch_ms": r["ms"] / r["launches"], "launches": r["launches"],
+           "algorithmic_per_launch": r["per_launch"]}
     return out
 
 
@@ -201,12 +258,11 @@ def main():
     torch.cuda.empty_cache()
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_path(dd, torch, w, dd.FP64, U_d, tv_d, f_d, max(1, args.steps // 2), 0)
+        fp64 = run_path(dd, torch, w, dd.FP64, U_d, tv_d, f_d, max(1, args.steps // 2), args.warmup)
         fp64["ctx"].close()
         del fp64["ctx"], fp64["u"]
         torch.cuda.empty_cache()
     ms = sum(mixed["step_ms"]) / len(mixed["step_ms"])
-    dom = roof["dslash_mixed16"]
     line = {
         "metric": "time-to-solution (rel.res 1e-10) 32^3x64, mixed vs FP64; dslash/D_c HBM GB/s",
         "value": ms / 1e3,
@@ -226,15 +282,17 @@ def main():
         "outer_iterations": st["outer_iterations"],
         "coarse_iterations_max": st["coarse_iterations_max"],
         "relres_max": max(st["relres"]),
-        "kernels": roof,
-        "roofline": {"bound": "hbm", "kernel": "dslash_mixed16", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "kernel_times_ms": {k: round(v[0] / args.steps, 3) for k, v in mixed["kernel_times"].items()},
+        "kernels_isolated": roof,
+        "roofline": dominant_roofline(w, mixed["kernel_times"], dd.MIXED16),
     }
     if fp64:
         f64ms = sum(fp64["step_ms"]) / len(fp64["step_ms"])
         line["fp64"] = {"ms_per_step": f64ms, "setup_ms": sum(fp64["setup_ms"]) / len(fp64["setup_ms"]),
                         "solve_ms": sum(fp64["solve_ms"]) / len(fp64["solve_ms"]),
-                        "outer_iterations": fp64["stats"]["outer_iterations"]}
+                        "outer_iterations": fp64["stats"]["outer_iterations"],
+                        "kernel_times_ms": {k: round(v[0] / max(1, args.steps // 2), 3)
+                                            for k, v in fp64["kernel_times"].items()}}
         line["speedup_mixed_vs_fp64"] = f64ms / ms
     if not args.no_cpu:
         try:

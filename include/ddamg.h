@@ -203,8 +203,28 @@ int dirac_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs, in
  * with coarse sites in the internal order (even coarse sites first). */
 int coarse_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs);
 
-/* Geometry queries: number of sites, blocks, and sizes in bytes of one
- * internal fine / coarse field of one rhs for a precision. */
+/* Per-kernel-class timing for profiling: when enabled, every launch of the
+ * classes below is bracketed by HIP events recorded on the context's stream
+ * and the elapsed times are summed (the brackets add a few microseconds of
+ * host overhead per launch).  ddamg_set_kernel_timing(ctx, on) zeroes the
+ * sums; ddamg_get_kernel_times fills ms[k] (total milliseconds), count[k]
+ * (timed launch groups) and rhs[k] (right-hand sides summed over those
+ * groups) for k < n, synchronising the stream first. */
+#define DDAMG_KERNEL_SAP 0              /* one SAP colour phase (Alg. 3) */
+#define DDAMG_KERNEL_DSLASH 1           /* outer matvec w = D z (FP64 links) */
+#define DDAMG_KERNEL_RESTRICT 2         /* y_c = R y (Eq. R) */
+#define DDAMG_KERNEL_PROLONG 3          /* x = P x_c */
+#define DDAMG_KERNEL_COARSE 4           /* D_c stencil pieces and D_ee^{-1} */
+#define DDAMG_KERNEL_COARSE_GS 5        /* coarse GMRES Gram-Schmidt */
+#define DDAMG_KERNEL_OUTER_GS 6         /* outer FGMRES Gram-Schmidt */
+#define DDAMG_KERNEL_SETUP_QR 7         /* aggregate orthonormalisation (Alg. 5) */
+#define DDAMG_KERNEL_SETUP_GALERKIN 8   /* D_ij P_j and its restriction (Eq. cgo) */
+#define DDAMG_KERNEL_RESIDUAL 9         /* true residual f - D u at restarts (FP64) */
+#define DDAMG_NKERNEL_KINDS 10
+int ddamg_set_kernel_timing(ddamg_ctx* ctx, int on);
+int ddamg_get_kernel_times(ddamg_ctx* ctx, double* ms, int64_t* count, int64_t* rhs, int n);
+
+/* Geometry queries: number of sites and of blocks. */
 int64_t ddamg_volume(const ddamg_ctx* ctx);
 int32_t ddamg_nblocks(const ddamg_ctx* ctx);
 

@@ -25,8 +25,10 @@ EXPORTS = (
     "mg_setup", "ddamg_import_basis", "ddamg_export_basis", "ddamg_export_tv", "ddamg_export_coarse",
     "ddamg_export_clover", "mg_apply", "dirac_apply", "coarse_apply", "mg_restrict", "mg_prolong", "solve",
     "ddamg_get_stats", "ddamg_reset_stats", "dirac_apply_internal", "coarse_apply_internal", "ddamg_volume",
-    "ddamg_nblocks",
+    "ddamg_nblocks", "ddamg_set_kernel_timing", "ddamg_get_kernel_times",
 )
+KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
+                "setup_galerkin", "residual")
 
 
 class DDAMGError(RuntimeError):
@@ -90,6 +92,9 @@ def _load():
         "coarse_apply_internal": (i32, [vp, vp, vp, i32]),
         "ddamg_volume": (ctypes.c_int64, [vp]),
         "ddamg_nblocks": (ctypes.c_int32, [vp]),
+        "ddamg_set_kernel_timing": (i32, [vp, i32]),
+        "ddamg_get_kernel_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -247,3 +252,16 @@ class Context:
 
     def reset_stats(self):
         return self._check(lib.ddamg_reset_stats(self.h))
+
+    def set_kernel_timing(self, on):
+        return self._check(lib.ddamg_set_kernel_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{kind: (total ms, launch groups, rhs summed over them)} of the
+        per-kernel-class event timers."""
+        n = len(KERNEL_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        rhs = (ctypes.c_int64 * n)()
+        self._check(lib.ddamg_get_kernel_times(self.h, ms, cnt, rhs, n))
+        return {k: (ms[i], cnt[i], rhs[i]) for i, k in enumerate(KERNEL_KINDS)}

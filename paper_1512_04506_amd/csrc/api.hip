@@ -78,6 +78,74 @@ struct DevBuf {
 
 std::string g_create_error;
 
+// Opt-in per-kernel-class timing with HIP events recorded on the context's
+// stream around each launch; elapsed times are collected at the next
+// synchronisation point (or when many records are pending).
+struct KTimer {
+  bool on = false;
+  struct Rec {
+    int kind, nrhs;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  double ms[DDAMG_NKERNEL_KINDS] = {};
+  int64_t count[DDAMG_NKERNEL_KINDS] = {};
+  int64_t rhs[DDAMG_NKERNEL_KINDS] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw Fail{DDAMG_EHIP, "hipEventCreate failed"};
+    return e;
+  }
+  template <typename F>
+  void run(int kind, int nrhs, hipStream_t st, F&& f) {
+    if (!on) {
+      f();
+      return;
+    }
+    hipEvent_t a = get(), b = get();
+    (void)hipEventRecord(a, st);
+    f();
+    (void)hipEventRecord(b, st);
+    pending.push_back({kind, nrhs, a, b});
+    if (pending.size() >= 2048) collect();
+  }
+  void collect() {
+    for (auto& r : pending) {
+      (void)hipEventSynchronize(r.b);
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.kind] += t;
+        count[r.kind] += 1;
+        rhs[r.kind] += r.nrhs;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    for (int k = 0; k < DDAMG_NKERNEL_KINDS; ++k) {
+      ms[k] = 0.0;
+      count[k] = 0;
+      rhs[k] = 0;
+    }
+  }
+  ~KTimer() {
+    for (auto& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace
 
 struct SolverBase;
@@ -90,7 +158,7 @@ struct ddamg_ctx {
   // FP64 master fields and the derived storage precisions
   DevBuf U64, A64, U32, A32, Uh, Uhs, Ah, Ahs;
   // tables
-  DevBuf colour_blocks, b2i, i2b, nbr;
+  DevBuf nbr;
   DevBuf status;
   int* h_flags = nullptr;        // pinned host mirrors of small device arrays
   double* h_dbl = nullptr;       // [128]
@@ -99,6 +167,7 @@ struct ddamg_ctx {
   DevBuf stage_in, stage_out;
   size_t stage_rhs = 0;
   std::unique_ptr<SolverBase> sol;
+  KTimer kt;
   bool setup_done = false;
   ddamg_stats stats{};
 
@@ -114,7 +183,14 @@ struct ddamg_ctx {
     stage_out.alloc<cx<double>>(n);
     stage_rhs = nrhs;
   }
-  void sync() { HIPCK(hipStreamSynchronize(st)); }
+  void sync() {
+    HIPCK(hipStreamSynchronize(st));
+    if (!kt.pending.empty()) kt.collect();
+  }
+  template <typename F>
+  void timed(int kind, int nrhs, F&& f) {
+    kt.run(kind, nrhs, st, f);
+  }
   void free_pinned() {
     if (h_flags) (void)hipHostFree(h_flags);
     if (h_dbl) (void)hipHostFree(h_dbl);
@@ -193,6 +269,18 @@ struct Solver final : SolverBase {
   DevBuf Wq, Wsc, Dq, Dsc, Dinv, tv;
   // fine work vectors (T): y, x, r [maxr][12][V]
   DevBuf fy, fx;
+  // setup workspace, allocated at the first setup and kept: FP64 copy of
+  // the test vectors for the Gram-Schmidt, dequantised basis, D_c
+  // accumulation buffer and one chunk of D_ij P_j columns
+  DevBuf ws_Wd, ws_Wt, ws_D, ws_Z;
+  static constexpr int GAL_CHUNK = 8;
+  void ensure_setup_ws() {
+    if (ws_Wd.p) return;
+    ws_Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
+    ws_Wt.alloc<cx<T>>((size_t)g.ntv * fsz());
+    ws_D.alloc<cx<T>>((size_t)g.nblocks * 9 * g.nc * g.nc);
+    ws_Z.alloc<cx<T>>((size_t)std::min(g.ntv, GAL_CHUNK) * fsz());
+  }
   // coarse work vectors (T)
   DevBuf yc, xc, te, ue, bo, cw, cV;
   Krylov ck;
@@ -250,7 +338,7 @@ struct Solver final : SolverBase {
   void sap(cx<T>* x, const cx<T>* y, int nrhs, int nu) {
     for (int n = 0; n < nu; ++n)
       for (int col = 0; col < 2; ++col)
-        launch_sap_phase<T, S>(x, y, gv, g, c->colour_blocks.get<int>(), col, c->p.n_mr, nrhs, st);
+        c->timed(DDAMG_KERNEL_SAP, nrhs, [&] { launch_sap_phase<T, S>(x, y, gv, g, col, c->p.n_mr, nrhs, st); });
   }
 
   // -------------------------------------------------------- coarse solve
@@ -258,11 +346,18 @@ struct Solver final : SolverBase {
   // (v and w: odd-site vectors with rhs strides vstr and wstr)
   void schur(cx<T>* w, size_t wstr, const cx<T>* v, size_t vstr, int nrhs) {
     const CoarseView<S> C = cv();
-    launch_coarse_stencil<T, S>(te.get<cx<T>>(), esz(), 0, g.neven, nullptr, 0, nullptr, 0, 0, (T)0, v, vstr, g.neven,
-                                (T)1, C, g, nrhs, st);
-    launch_block_matvec<T>(ue.get<cx<T>>(), esz(), Dinv.get<cx<T>>(), te.get<cx<T>>(), esz(), g.neven, g.nc, nrhs, st);
-    launch_coarse_stencil<T, S>(w, wstr, g.neven, nodd(), nullptr, 0, v, vstr, g.neven, (T)1, ue.get<cx<T>>(), esz(),
-                                0, (T)-1, C, g, nrhs, st);
+    c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
+      launch_coarse_stencil<T, S>(te.get<cx<T>>(), esz(), 0, g.neven, nullptr, 0, nullptr, 0, 0, (T)0, v, vstr,
+                                  g.neven, (T)1, C, g, nrhs, st);
+    });
+    c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
+      launch_block_matvec<T>(ue.get<cx<T>>(), esz(), Dinv.get<cx<T>>(), te.get<cx<T>>(), esz(), g.neven, g.nc, nrhs,
+                             st);
+    });
+    c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
+      launch_coarse_stencil<T, S>(w, wstr, g.neven, nodd(), nullptr, 0, v, vstr, g.neven, (T)1, ue.get<cx<T>>(),
+                                  esz(), 0, (T)-1, C, g, nrhs, st);
+    });
   }
 
   int read_any_active(const Krylov& k, int nrhs) {
@@ -326,7 +421,7 @@ struct Solver final : SolverBase {
       for (; k < m && its < maxit; ++k) {
         cx<T>* w = Vb + (size_t)(k + 1) * vsj;
         schur(w, vsr, Vb + (size_t)k * vsj, vsr, nrhs);
-        cgs2(ck, Vb, vsj, vsr, k, w, vsr, osz(), nrhs);
+        c->timed(DDAMG_KERNEL_COARSE_GS, nrhs, [&] { cgs2(ck, Vb, vsj, vsr, k, w, vsr, osz(), nrhs); });
         launch_arnoldi_column(ck.st, k, ck.h1.get<cx<double>>(), ck.h2.get<cx<double>>(), ck.ldh,
                               ck.n2.get<cx<double>>(), 1, nrhs, st);
         launch_scale<T, T>(w, vsr, w, vsr, ck.inv_h.get<double>(), osz(), nrhs, nullptr, st);
@@ -353,9 +448,11 @@ struct Solver final : SolverBase {
   // -------------------------------------------------------------- V-cycle
   // x = M^{-1} y (Alg. 1): coarse-grid correction then SAP from it
   void vcycle(cx<T>* x, const cx<T>* y, int nrhs) {
-    launch_restrict<T, S>(yc.get<cx<T>>(), csz(), g.nc, y, fsz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    c->timed(DDAMG_KERNEL_RESTRICT, nrhs,
+             [&] { launch_restrict<T, S>(yc.get<cx<T>>(), csz(), g.nc, y, fsz(), bv(), g, nrhs, st); });
     coarse_solve(xc.get<cx<T>>(), yc.get<cx<T>>(), nrhs);
-    launch_prolong<T, S>(x, fsz(), xc.get<cx<T>>(), csz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    c->timed(DDAMG_KERNEL_PROLONG, nrhs,
+             [&] { launch_prolong<T, S>(x, fsz(), xc.get<cx<T>>(), csz(), bv(), g, nrhs, st); });
     sap(x, y, nrhs, c->p.nu);
     check_launch("vcycle");
   }
@@ -380,13 +477,13 @@ struct Solver final : SolverBase {
   void build_coarse_from(cx<double>* Wd) {
     launch_quantize_basis<S>(Wq.get<stc_t<S>>(), Wsc.get<float>(), Wd, g, st);
     const size_t nc = g.nc, nn = nc * nc;
-    DevBuf Dacc, Wt, Z;
-    cx<T>* D = Dacc.alloc<cx<T>>((size_t)g.nblocks * 9 * nn);
+    ensure_setup_ws();
+    cx<T>* D = ws_D.get<cx<T>>();
     HIPCK(hipMemsetAsync(D, 0, sizeof(cx<T>) * g.nblocks * 9 * nn, st));
-    cx<T>* Wtp = Wt.alloc<cx<T>>((size_t)g.ntv * fsz());
+    cx<T>* Wtp = ws_Wt.get<cx<T>>();
     launch_dequantize_basis<T, S>(Wtp, bv(), g, st);
-    const int CH = std::min(g.ntv, 8);
-    cx<T>* Zp = Z.alloc<cx<T>>((size_t)CH * fsz());
+    const int CH = std::min(g.ntv, (int)GAL_CHUNK);
+    cx<T>* Zp = ws_Z.get<cx<T>>();
     for (int hp = 0; hp < 2; ++hp)
       for (int a0 = 0; a0 < g.ntv; a0 += CH) {
         const int na = std::min(CH, g.ntv - a0);
@@ -395,9 +492,11 @@ struct Solver final : SolverBase {
           const int mode = piece == 0 ? DS_BLOCK : DS_CROSS_FWD;
           const int mu = piece == 0 ? 0 : piece - 1;
           const int slot = piece == 0 ? 0 : 1 + 2 * mu;
-          launch_dslash<T, T, T, T>(Zp, in, gva, g, na, mode, mu, hp, fsz(), fsz(), st);
           cx<T>* out = D + (size_t)slot * nn + (size_t)(hp * g.ntv + a0) * nc;
-          launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, c->b2i.get<int>(), na, st);
+          c->timed(DDAMG_KERNEL_SETUP_GALERKIN, na, [&] {
+            launch_dslash<T, T, T, T>(Zp, in, gva, g, na, mode, mu, hp, fsz(), fsz(), st);
+            launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, na, st);
+          });
         }
       }
     launch_dagger_fill<T>(D, c->nbr.get<int>(), g, st);
@@ -413,11 +512,11 @@ struct Solver final : SolverBase {
 
   // Gram-Schmidt of the current test vectors on every aggregate, then D_c
   void build_coarse() {
-    DevBuf Wd;
-    cx<double>* W = Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
+    ensure_setup_ws();
+    cx<double>* W = ws_Wd.get<cx<double>>();
     launch_copy<double, T>(W, fsz(), tv.get<cx<T>>(), fsz(), fsz(), g.ntv, st);
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
-    launch_aggregate_qr(W, g, c->status.get<int>(), st);
+    c->timed(DDAMG_KERNEL_SETUP_QR, g.ntv, [&] { launch_aggregate_qr(W, g, c->status.get<int>(), st); });
     check_launch("aggregate qr");
     int stat = 0;
     HIPCK(hipMemcpyAsync(&stat, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -449,8 +548,8 @@ struct Solver final : SolverBase {
   }
 
   void import_basis(const double* Wc) override {
-    DevBuf Wd;
-    cx<double>* W = Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
+    ensure_setup_ws();
+    cx<double>* W = ws_Wd.get<cx<double>>();
     launch_spinor_to_internal<double>(W, reinterpret_cast<const cx<double>*>(Wc), g, g.ntv, st);
     launch_copy<T, double>(tv.get<cx<T>>(), fsz(), W, fsz(), fsz(), g.ntv, st);
     build_coarse_from(W);
@@ -468,7 +567,7 @@ struct Solver final : SolverBase {
     c->sync();
   }
   void export_coarse(double* out) override {
-    launch_export_coarse<T, S>(reinterpret_cast<cx<double>*>(out), cv(), g, c->i2b.get<int>(), st);
+    launch_export_coarse<T, S>(reinterpret_cast<cx<double>*>(out), cv(), g, st);
     c->sync();
   }
 
@@ -484,20 +583,18 @@ struct Solver final : SolverBase {
                                 (T)1, cv(), g, nrhs, st);
   }
   void coarse_canon(double* out, const double* in, int nrhs) override {
-    launch_coarse_to_internal<T>(yc.get<cx<T>>(), reinterpret_cast<const cx<double>*>(in), g, c->b2i.get<int>(), nrhs,
-                                 st);
+    launch_coarse_to_internal<T>(yc.get<cx<T>>(), reinterpret_cast<const cx<double>*>(in), g, nrhs, st);
     coarse_internal(xc.get<cx<T>>(), yc.get<cx<T>>(), nrhs);
-    launch_coarse_to_canonical<T>(reinterpret_cast<cx<double>*>(out), xc.get<cx<T>>(), g, c->b2i.get<int>(), nrhs, st);
+    launch_coarse_to_canonical<T>(reinterpret_cast<cx<double>*>(out), xc.get<cx<T>>(), g, nrhs, st);
   }
   void restrict_canon(double* ycn, const double* y, int nrhs) override {
     launch_spinor_to_internal<T>(fy.get<cx<T>>(), reinterpret_cast<const cx<double>*>(y), g, nrhs, st);
-    launch_restrict<T, S>(yc.get<cx<T>>(), csz(), g.nc, fy.get<cx<T>>(), fsz(), bv(), g, c->b2i.get<int>(), nrhs, st);
-    launch_coarse_to_canonical<T>(reinterpret_cast<cx<double>*>(ycn), yc.get<cx<T>>(), g, c->b2i.get<int>(), nrhs, st);
+    launch_restrict<T, S>(yc.get<cx<T>>(), csz(), g.nc, fy.get<cx<T>>(), fsz(), bv(), g, nrhs, st);
+    launch_coarse_to_canonical<T>(reinterpret_cast<cx<double>*>(ycn), yc.get<cx<T>>(), g, nrhs, st);
   }
   void prolong_canon(double* x, const double* xcn, int nrhs) override {
-    launch_coarse_to_internal<T>(xc.get<cx<T>>(), reinterpret_cast<const cx<double>*>(xcn), g, c->b2i.get<int>(), nrhs,
-                                 st);
-    launch_prolong<T, S>(fx.get<cx<T>>(), fsz(), xc.get<cx<T>>(), csz(), bv(), g, c->b2i.get<int>(), nrhs, st);
+    launch_coarse_to_internal<T>(xc.get<cx<T>>(), reinterpret_cast<const cx<double>*>(xcn), g, nrhs, st);
+    launch_prolong<T, S>(fx.get<cx<T>>(), fsz(), xc.get<cx<T>>(), csz(), bv(), g, nrhs, st);
     launch_spinor_to_canonical<T>(reinterpret_cast<cx<double>*>(x), fx.get<cx<T>>(), g, nrhs, st);
   }
 
@@ -555,7 +652,8 @@ struct Solver final : SolverBase {
     std::vector<double> relres(nrhs, 0.0);
     for (;;) {
       // true residual r = f - D u in FP64, into V_0
-      launch_dslash<double, double, double, double>(w, u, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
+      c->timed(DDAMG_KERNEL_RESIDUAL, nrhs,
+               [&] { launch_dslash<double, double, double, double>(w, u, g64, g, nrhs, DS_FULL, 0, -1, n, n, st); });
       launch_sub<double>(V, n, f, n, w, n, n, nrhs, st);
       launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), V, 0, n, 1, V, n, n, nrhs, nullptr,
                           st);
@@ -585,11 +683,13 @@ struct Solver final : SolverBase {
         vcycle(zk, fy.get<cx<T>>(), nrhs);
         // w = D z_k (FP64 operator)
         cx<double>* wk = V + (size_t)(k + 1) * vsj;
-        if constexpr (std::is_same<T, double>::value)
-          launch_dslash<double, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
-        else
-          launch_dslash<float, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
-        cgs2(ok, V, vsj, n, k, wk, n, n, nrhs);
+        c->timed(DDAMG_KERNEL_DSLASH, nrhs, [&] {
+          if constexpr (std::is_same<T, double>::value)
+            launch_dslash<double, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
+          else
+            launch_dslash<float, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
+        });
+        c->timed(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { cgs2(ok, V, vsj, n, k, wk, n, n, nrhs); });
         launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), ok.h2.get<cx<double>>(), ok.ldh,
                               ok.n2.get<cx<double>>(), 1, nrhs, st);
         launch_scale<double, double>(wk, n, wk, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
@@ -694,55 +794,22 @@ int validate(const ddamg_params* p, std::string& why) {
 }
 
 void build_tables(ddamg_ctx* c) {
-  const Geom& g = c->g;
-  std::vector<int> colour(g.nblocks), b2i(g.nblocks), i2b(g.nblocks), nbr((size_t)g.nblocks * 9);
-  std::vector<int> cb;
-  cb.reserve(g.nblocks);
-  auto bcoord = [&](int b, int bc[4]) {
-    bc[0] = b % g.NB[0];
-    b /= g.NB[0];
-    bc[1] = b % g.NB[1];
-    b /= g.NB[1];
-    bc[2] = b % g.NB[2];
-    bc[3] = b / g.NB[2];
-  };
-  auto bindex = [&](const int bc[4]) { return bc[0] + g.NB[0] * (bc[1] + g.NB[1] * (bc[2] + g.NB[2] * bc[3])); };
-  for (int b = 0; b < g.nblocks; ++b) {
+  Geom& g = c->g;
+  g.neven = g.nblocks / 2;
+  std::vector<int> nbr((size_t)g.nblocks * 9);
+  for (int ci = 0; ci < g.nblocks; ++ci) {
     int bc[4];
-    bcoord(b, bc);
-    colour[b] = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
-  }
-  for (int col = 0; col < 2; ++col)
-    for (int b = 0; b < g.nblocks; ++b)
-      if (colour[b] == col) cb.push_back(b);
-  int ne = 0;
-  for (int b = 0; b < g.nblocks; ++b)
-    if (colour[b] == 0) i2b[ne++] = b;
-  int k = ne;
-  for (int b = 0; b < g.nblocks; ++b)
-    if (colour[b] == 1) i2b[k++] = b;
-  for (int i = 0; i < g.nblocks; ++i) b2i[i2b[i]] = i;
-  for (int b = 0; b < g.nblocks; ++b) {
-    int bc[4];
-    bcoord(b, bc);
-    const int ci = b2i[b];
+    int_block_coords(g, ci, bc);
     nbr[(size_t)ci * 9] = ci;
     for (int mu = 0; mu < 4; ++mu)
       for (int d = 0; d < 2; ++d) {
         int e[4] = {bc[0], bc[1], bc[2], bc[3]};
         e[mu] = (e[mu] + (d == 0 ? 1 : -1) + g.NB[mu]) % g.NB[mu];
-        nbr[(size_t)ci * 9 + 1 + 2 * mu + d] = b2i[bindex(e)];
+        nbr[(size_t)ci * 9 + 1 + 2 * mu + d] = block_to_int(g, e);
       }
   }
-  c->g.neven = ne;
-  auto up = [&](DevBuf& d, const std::vector<int>& h) {
-    d.alloc<int>(h.size());
-    HIPCK(hipMemcpy(d.get<int>(), h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
-  };
-  up(c->colour_blocks, cb);
-  up(c->b2i, b2i);
-  up(c->i2b, i2b);
-  up(c->nbr, nbr);
+  c->nbr.alloc<int>(nbr.size());
+  HIPCK(hipMemcpy(c->nbr.get<int>(), nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
 }
 
 }  // namespace
@@ -816,6 +883,8 @@ int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg
     }
     g.ntv = p->ntv;
     g.nc = 2 * p->ntv;
+    g.lstr[0] = 1;
+    for (int mu = 1; mu < 4; ++mu) g.lstr[mu] = g.lstr[mu - 1] * g.bs[mu - 1];
     build_tables(c.get());
     HIPCK(hipHostMalloc((void**)&c->h_flags, 64 * sizeof(int), hipHostMallocDefault));
     HIPCK(hipHostMalloc((void**)&c->h_dbl, 128 * sizeof(double), hipHostMallocDefault));
@@ -1147,6 +1216,29 @@ int ddamg_reset_stats(ddamg_ctx* c) {
   if (!c) return DDAMG_EARG;
   if (c->sol) c->sol->reset_coarse_stats();
   return DDAMG_OK;
+}
+
+int ddamg_set_kernel_timing(ddamg_ctx* c, int on) {
+  if (!c) return DDAMG_EARG;
+  GUARD_BEGIN
+  c->sync();
+  c->kt.reset();
+  c->kt.on = on != 0;
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_get_kernel_times(ddamg_ctx* c, double* ms, int64_t* count, int64_t* rhs, int n) {
+  if (!c || !ms || !count || !rhs || n < 1) return DDAMG_EARG;
+  GUARD_BEGIN
+  c->sync();
+  for (int k = 0; k < n; ++k) {
+    ms[k] = k < DDAMG_NKERNEL_KINDS ? c->kt.ms[k] : 0.0;
+    count[k] = k < DDAMG_NKERNEL_KINDS ? c->kt.count[k] : 0;
+    rhs[k] = k < DDAMG_NKERNEL_KINDS ? c->kt.rhs[k] : 0;
+  }
+  return DDAMG_OK;
+  GUARD_END
 }
 
 int64_t ddamg_volume(const ddamg_ctx* c) { return c ? (int64_t)c->g.V : -1; }

@@ -81,45 +81,80 @@ __device__ inline void stc_store(__half2* p, size_t i, cx<double> v) {
 }
 
 // ---------------------------------------------------------------- geometry
+// Internal site order is block-major: site S = ci * vblock + l, where l is
+// the lexicographic site inside the block (x fastest) and ci the internal
+// block index.  Blocks are ordered by parity (sum of block coordinates mod 2,
+// i.e. the SAP colour and the coarse even/odd parity) and lexicographically
+// within a parity.  With an even number of blocks along x the rank of the
+// lexicographic block b inside its parity is b >> 1, so
+//   ci = parity(b) * nblocks / 2 + (b >> 1).
+// Every block's sites are contiguous, so block-local work (SAP, R, P,
+// aggregate Gram-Schmidt) reads whole cache lines; the coarse-site order of
+// coarse vectors and D_c is the same ci.
 struct Geom {
   int L[4];      // lattice extents x, y, z, t
   int bs[4];     // block extents
   int NB[4];     // block-lattice extents
+  int lstr[4];   // strides of the local coordinates inside a block
   int V;         // sites
   int vblock;    // sites per block
   int nblocks;   // blocks = coarse sites
   int ntv;       // test vectors
   int nc;        // coarse components per site = 2 ntv
-  int neven;     // coarse sites of even parity (internal order: even first)
+  int neven;     // coarse sites of even parity (= nblocks / 2)
 };
 
-__host__ __device__ inline void site_coords(const Geom& g, int s, int c[4]) {
-  c[0] = s % g.L[0]; s /= g.L[0];
-  c[1] = s % g.L[1]; s /= g.L[1];
-  c[2] = s % g.L[2];
-  c[3] = s / g.L[2];
+__host__ __device__ inline int lex_block(const Geom& g, const int bc[4]) {
+  return bc[0] + g.NB[0] * (bc[1] + g.NB[1] * (bc[2] + g.NB[2] * bc[3]));
 }
-__host__ __device__ inline int site_index(const Geom& g, const int c[4]) {
-  return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+__host__ __device__ inline int block_to_int(const Geom& g, const int bc[4]) {
+  const int p = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+  return p * g.neven + (lex_block(g, bc) >> 1);
 }
-// lexicographic block index of a site
-__host__ __device__ inline int block_of(const Geom& g, const int c[4]) {
-  return c[0] / g.bs[0] + g.NB[0] * (c[1] / g.bs[1] + g.NB[1] * (c[2] / g.bs[2] + g.NB[2] * (c[3] / g.bs[3])));
+// block coordinates of internal block ci
+__host__ __device__ inline void int_block_coords(const Geom& g, int ci, int bc[4]) {
+  const int p = ci >= g.neven ? 1 : 0;
+  int b = 2 * (ci - p * g.neven);
+  int t = b;
+  bc[0] = t % g.NB[0]; t /= g.NB[0];
+  bc[1] = t % g.NB[1]; t /= g.NB[1];
+  bc[2] = t % g.NB[2];
+  bc[3] = t / g.NB[2];
+  if (((bc[0] + bc[1] + bc[2] + bc[3]) & 1) != p) bc[0] += 1;  // the odd partner of the pair along x
 }
-// global site of local site l in lexicographic block b
-__host__ __device__ inline int block_site(const Geom& g, int b, int l, int c[4]) {
-  int bc[4];
-  bc[0] = b % g.NB[0]; b /= g.NB[0];
-  bc[1] = b % g.NB[1]; b /= g.NB[1];
-  bc[2] = b % g.NB[2];
-  bc[3] = b / g.NB[2];
-  int lc[4];
+__host__ __device__ inline void local_coords(const Geom& g, int l, int lc[4]) {
   lc[0] = l % g.bs[0]; l /= g.bs[0];
   lc[1] = l % g.bs[1]; l /= g.bs[1];
   lc[2] = l % g.bs[2];
   lc[3] = l / g.bs[2];
+}
+// global coordinates of internal site S
+__host__ __device__ inline void site_coords(const Geom& g, int S, int c[4]) {
+  int bc[4], lc[4];
+  int_block_coords(g, S / g.vblock, bc);
+  local_coords(g, S % g.vblock, lc);
   for (int m = 0; m < 4; ++m) c[m] = bc[m] * g.bs[m] + lc[m];
-  return site_index(g, c);
+}
+// internal site of global coordinates c
+__host__ __device__ inline int site_index(const Geom& g, const int c[4]) {
+  int bc[4], l = 0;
+  for (int m = 0; m < 4; ++m) bc[m] = c[m] / g.bs[m];
+  for (int m = 3; m >= 0; --m) l = l * g.bs[m] + (c[m] - bc[m] * g.bs[m]);
+  return block_to_int(g, bc) * g.vblock + l;
+}
+// MI355X has 8 XCDs with separate L2 caches and hands out consecutive
+// workgroup ids round-robin over them.  xcd_swizzle maps the hardware id to
+// a logical id such that each XCD works on one contiguous 1/8 of the
+// logical range (when the grid divides evenly), so neighbouring lattice
+// regions share an L2.
+__device__ inline int xcd_swizzle(int wg, int nwg) {
+  if (nwg % 8) return wg;
+  return (wg & 7) * (nwg >> 3) + (wg >> 3);
+}
+
+// lexicographic (canonical) index of global coordinates c
+__host__ __device__ inline int lex_site(const Geom& g, const int c[4]) {
+  return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }
 
 // Links [mu][9][V] (row-major 3x3 per link), clover [2][36][V]: per chirality
@@ -175,17 +210,17 @@ void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, con
 // SAP: one colour phase of multiplicative Schwarz with n_mr MR steps per
 // block, in place on x, for nrhs fields.
 template <typename T, typename S>
-void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, const int* colour_blocks,
-                      int colour, int n_mr, int nrhs, hipStream_t st);
+void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, int colour, int n_mr, int nrhs,
+                      hipStream_t st);
 
 // restriction / prolongation; coarse output addressed as
 // out[r * ostr_r + cint(b) * ostr_b + h * ntv + a]
 template <typename T, typename S>
 void launch_restrict(cx<T>* out, size_t ostr_r, size_t ostr_b, const cx<T>* y, size_t ystr, const BasisView<S>& bv,
-                     const Geom& g, const int* block_to_int, int nrhs, hipStream_t st);
+                     const Geom& g, int nrhs, hipStream_t st);
 template <typename T, typename S>
 void launch_prolong(cx<T>* x, size_t xstr, const cx<T>* xc, size_t cstr, const BasisView<S>& bv, const Geom& g,
-                    const int* block_to_int, int nrhs, hipStream_t st);
+                    int nrhs, hipStream_t st);
 
 // coarse stencil: for internal output sites [out_first, out_first + nout):
 // out = add + cs * D_self xs + cn * sum_{slot>0} D_slot xn(nbr)
@@ -212,14 +247,11 @@ void launch_quantize_coarse(stc_t<S>* Dq, float* Dsc, const cx<T>* Dc, const Geo
 template <typename T, typename S>
 void launch_invert_even_blocks(cx<T>* Dinv, const CoarseView<S>& cv, const Geom& g, int* status, hipStream_t st);
 template <typename T, typename S>
-void launch_export_coarse(cx<double>* out, const CoarseView<S>& cv, const Geom& g, const int* int_to_block,
-                          hipStream_t st);
+void launch_export_coarse(cx<double>* out, const CoarseView<S>& cv, const Geom& g, hipStream_t st);
 template <typename T>
-void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, const int* block_to_int, int nrhs,
-                               hipStream_t st);
+void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st);
 template <typename T>
-void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, const int* block_to_int, int nrhs,
-                                hipStream_t st);
+void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st);
 
 // BLAS on block vectors x[r * rstride + i], i < n, r < nrhs.
 // partial dots: part[(r * nvec + j) * nchunk + c]; final h[r * ldh + j].

@@ -70,11 +70,11 @@ __device__ inline void reconstruct(cx<T> acc[4][3], const Half2<T>& u, T coef) {
   }
 }
 
-template <typename Tin, typename Tc>
+template <typename Tin, typename Tc, bool CHI = true>
 __device__ inline void load_spinor(cx<Tc> p[4][3], const cx<Tin>* in, int s, size_t V, int chi_in, Tc sign) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp) {
-    bool keep = chi_in < 0 || (sp >> 1) == chi_in;
+    const bool keep = !CHI || chi_in < 0 || (sp >> 1) == chi_in;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       cx<Tc> v = cvt<Tc>(in[(size_t)(3 * sp + c) * V + s]);
@@ -113,11 +113,11 @@ __device__ inline void hop_spinor(cx<Tc> acc[4][3], const cx<Tc> p[4][3], const 
   reconstruct<MU, FWD, Tc>(acc, u, (Tc)-0.5);
 }
 
-template <int MU, bool FWD, typename Tin, typename Tc, typename S>
+template <int MU, bool FWD, typename Tin, typename Tc, typename S, bool CHI>
 __device__ inline void hop(cx<Tc> acc[4][3], const cx<Tin>* in, const GaugeView<S>& gv, int sn, int slink, size_t V,
                            int chi_in, Tc sign) {
   cx<Tc> p[4][3];
-  load_spinor<Tin, Tc>(p, in, sn, V, chi_in, sign);
+  load_spinor<Tin, Tc, CHI>(p, in, sn, V, chi_in, sign);
   hop_spinor<MU, FWD, Tc, S>(acc, p, gv, slink, V);
 }
 
@@ -150,14 +150,51 @@ __device__ inline void clover_apply(cx<Tc> acc[4][3], const cx<Tc> p[4][3], cons
   }
 }
 
+// Position of an internal site: block coordinates, local coordinates and
+// the local index, from which neighbours are found without a table.
+struct SitePos {
+  int S, ci, l;
+  int bc[4], lc[4];
+};
+
+__device__ inline SitePos site_pos(const Geom& g, int S) {
+  SitePos p;
+  p.S = S;
+  p.ci = S / g.vblock;
+  p.l = S - p.ci * g.vblock;
+  int_block_coords(g, p.ci, p.bc);
+  local_coords(g, p.l, p.lc);
+  return p;
+}
+
+// internal index of the forward / backward neighbour in direction mu
+__device__ inline int nbr_fwd(const Geom& g, const SitePos& p, int mu) {
+  if (p.lc[mu] < g.bs[mu] - 1) return p.S + g.lstr[mu];
+  int bc[4] = {p.bc[0], p.bc[1], p.bc[2], p.bc[3]};
+  bc[mu] = bc[mu] + 1 == g.NB[mu] ? 0 : bc[mu] + 1;
+  return block_to_int(g, bc) * g.vblock + p.l - p.lc[mu] * g.lstr[mu];
+}
+__device__ inline int nbr_bwd(const Geom& g, const SitePos& p, int mu) {
+  if (p.lc[mu] > 0) return p.S - g.lstr[mu];
+  int bc[4] = {p.bc[0], p.bc[1], p.bc[2], p.bc[3]};
+  bc[mu] = bc[mu] == 0 ? g.NB[mu] - 1 : bc[mu] - 1;
+  return block_to_int(g, bc) * g.vblock + p.l + (g.bs[mu] - 1) * g.lstr[mu];
+}
+
+// hops of direction MU selected by MODE: all (full D), inside the block
+// (block operator B), or the block-crossing forward / backward hops of
+// direction mu_sel.  A hop across the time boundary carries the factor -1.
 template <int MU, typename Tin, typename Tc, typename S, int MODE>
 __device__ inline void hops_mu(cx<Tc> acc[4][3], const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g,
-                               const int c[4], int s, int mu_sel, int chi_in) {
+                               const SitePos& p, int mu_sel, int chi_in) {
   const size_t V = g.V;
-  const int l = c[MU] % g.bs[MU];
+  const int l = p.lc[MU];
   bool do_f, do_b;
   if (MODE == DS_FULL) {
-    do_f = do_b = true;
+    // true at run time; being opaque to the compiler it keeps each hop in
+    // its own branch, so its loads are issued with its arithmetic instead of
+    // all being hoisted to the top of the kernel
+    do_f = do_b = g.V > 0;
   } else if (MODE == DS_BLOCK) {
     do_f = l != g.bs[MU] - 1;
     do_b = l != 0;
@@ -169,18 +206,30 @@ __device__ inline void hops_mu(cx<Tc> acc[4][3], const cx<Tin>* in, const GaugeV
     do_b = MU == mu_sel && l == 0;
   }
   if (do_f) {
-    int e[4] = {c[0], c[1], c[2], c[3]};
-    e[MU] = (c[MU] + 1 == g.L[MU]) ? 0 : c[MU] + 1;
-    Tc sign = (MU == 3 && c[3] == g.L[3] - 1) ? (Tc)-1 : (Tc)1;
-    hop<MU, true, Tin, Tc, S>(acc, in, gv, site_index(g, e), s, V, chi_in, sign);
+    const bool wrap = MU == 3 && l == g.bs[3] - 1 && p.bc[3] == g.NB[3] - 1;
+    hop<MU, true, Tin, Tc, S, MODE != DS_FULL>(acc, in, gv, nbr_fwd(g, p, MU), p.S, V, chi_in, wrap ? (Tc)-1 : (Tc)1);
   }
   if (do_b) {
-    int e[4] = {c[0], c[1], c[2], c[3]};
-    e[MU] = (c[MU] == 0) ? g.L[MU] - 1 : c[MU] - 1;
-    int sb = site_index(g, e);
-    Tc sign = (MU == 3 && c[3] == 0) ? (Tc)-1 : (Tc)1;
-    hop<MU, false, Tin, Tc, S>(acc, in, gv, sb, sb, V, chi_in, sign);
+    const bool wrap = MU == 3 && l == 0 && p.bc[3] == 0;
+    const int sb = nbr_bwd(g, p, MU);
+    hop<MU, false, Tin, Tc, S, MODE != DS_FULL>(acc, in, gv, sb, sb, V, chi_in, wrap ? (Tc)-1 : (Tc)1);
   }
+}
+
+// All four directions, one after the other.  The empty asm statements with a
+// memory clobber keep the compiler from hoisting the loads of later
+// directions above the arithmetic of earlier ones, which would keep all
+// eight neighbours live at once and overflow the register file.
+template <typename Tin, typename Tc, typename S, int MODE>
+__device__ inline void hops_all(cx<Tc> acc[4][3], const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g,
+                                const SitePos& p, int mu_sel, int chi_in) {
+  hops_mu<0, Tin, Tc, S, MODE>(acc, in, gv, g, p, mu_sel, chi_in);
+  asm volatile("" ::: "memory");
+  hops_mu<1, Tin, Tc, S, MODE>(acc, in, gv, g, p, mu_sel, chi_in);
+  asm volatile("" ::: "memory");
+  hops_mu<2, Tin, Tc, S, MODE>(acc, in, gv, g, p, mu_sel, chi_in);
+  asm volatile("" ::: "memory");
+  hops_mu<3, Tin, Tc, S, MODE>(acc, in, gv, g, p, mu_sel, chi_in);
 }
 
 }  // namespace dev

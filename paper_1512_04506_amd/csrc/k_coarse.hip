@@ -23,147 +23,246 @@ __device__ inline T wave_sum(T v) {
 }
 
 // ----------------------------------------------------------- restriction
-// One wave per (block, chirality h, test vector a); lanes stride over the
-// block's sites; up to RC right-hand sides accumulate per basis load.
-constexpr int RC = 8;
+// One workgroup per block, one lane per site of the block (its sites are
+// contiguous in the block-major layout, so every load is coalesced).  For a
+// tile of RT right-hand sides (kept in registers) and AT test vectors at a
+// time each lane forms the 6-component partial products of its site for
+// both chiralities; the 64 lanes of a wave are then summed by a butterfly
+// reduce-scatter (63 shuffle-adds for 32 values) and the waves through LDS.
+// Register tiles: RT right-hand sides x AT test vectors per pass, NV real
+// partial sums per lane (smaller in FP64 to stay within the register file).
+template <typename T>
+struct RTile {
+  static constexpr int RT = sizeof(T) == 8 ? 2 : 4;
+  static constexpr int AT = sizeof(T) == 8 ? 1 : 2;
+  static constexpr int NV = AT * 2 * RT * 2;
+};
+constexpr int RT = 4;  // rhs tile of the prolongation
+
+// One halving step of the butterfly, unrolled at compile time so that every
+// register index is static: lanes with bit HALF set keep the upper half of
+// their values and receive the partner's upper half, the others the lower.
+template <int HALF, int NV, typename T>
+__device__ inline void rs_step(T v[NV], int lane) {
+  const bool up = (lane & HALF) != 0;
+#pragma unroll
+  for (int j = 0; j < HALF; ++j) {
+    const T send = up ? v[j] : v[j + HALF];
+    const T keep = up ? v[j + HALF] : v[j];
+    v[j] = keep + __shfl_xor(send, HALF, 64);
+  }
+  if constexpr (HALF > 1) rs_step<HALF / 2, NV, T>(v, lane);
+}
+
+// v[0..NV-1] (NV a power of two <= 32): after the call lane i holds the sum
+// over the 64 lanes of v[i % NV] (full sums over the lane bits >= NV first,
+// then a reduce-scatter over the lower bits)
+template <int NV, typename T>
+__device__ inline T reduce_scatter(T v[NV], int lane) {
+#pragma unroll
+  for (int o = 32; o >= NV; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] += __shfl_xor(v[j], o, 64);
+  rs_step<NV / 2, NV, T>(v, lane);
+  return v[0];
+}
 
 template <typename T, typename S>
-__global__ __launch_bounds__(64) void restrict_kernel(cx<T>* __restrict__ out, size_t ostr_r, size_t ostr_b,
-                                                      const cx<T>* __restrict__ y, size_t ystr, BasisView<S> bv,
-                                                      Geom g, const int* __restrict__ b2i, int nrhs) {
-  const int b = blockIdx.x;
-  const int h = blockIdx.y / g.ntv;
-  const int a = blockIdx.y % g.ntv;
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void restrict_kernel(cx<T>* __restrict__ out, size_t ostr_r, size_t ostr_b,
+                                                       const cx<T>* __restrict__ y, size_t ystr, BasisView<S> bv,
+                                                       Geom g, int nrhs) {
+  constexpr int RT = RTile<T>::RT, AT = RTile<T>::AT, NV = RTile<T>::NV;
+  constexpr int MAXAT = 32 / AT;  // ntv <= 32
+  __shared__ T red[4][MAXAT][NV];
+  const int ci = blockIdx.x;
+  const int l = threadIdx.x;
+  const int lane = l & 63, w = l >> 6;
+  const int nw = blockDim.x >> 6;
+  const bool act = l < g.vblock;
   const size_t V = g.V;
-  const int ci = b2i[b];
-  for (int r0 = 0; r0 < nrhs; r0 += RC) {
-    const int nr = min(RC, nrhs - r0);
-    cx<T> acc[RC];
+  const size_t site = (size_t)ci * g.vblock + (act ? l : 0);
+  const int nat = (g.ntv + AT - 1) / AT;
+  for (int r0 = 0; r0 < nrhs; r0 += RT) {
+    const int nr = min(RT, nrhs - r0);
+    // Every load below is unconditional (clamped to valid addresses and
+    // masked by a factor instead): a load guarded by a value that is itself
+    // loaded would serialise the memory accesses of the whole loop.
+    cx<T> yv[RT][12];
 #pragma unroll
-    for (int j = 0; j < RC; ++j) acc[j] = mk((T)0, (T)0);
-    for (int l = lane; l < g.vblock; l += 64) {
-      int c[4];
-      const int s = block_site(g, b, l, c);
-      T sc = (T)1;
-      if constexpr (is_half<S>()) sc = (T)bv.Wsc[(size_t)a * V + s];
+    for (int j = 0; j < RT; ++j) {
+      const T m = (act && j < nr) ? (T)1 : (T)0;
+      const size_t r = (size_t)min(r0 + j, nrhs - 1);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int comp = 6 * h + k;
-        cx<T> w = sc * ldc<T>(bv.W, ((size_t)a * 12 + comp) * V + s);
+      for (int k = 0; k < 12; ++k) yv[j][k] = m * y[r * ystr + (size_t)k * V + site];
+    }
+    // no barrier inside this loop: each wave parks its reduced values per
+    // test-vector tile and runs ahead
+    for (int at = 0; at < nat; ++at) {
+      const int a0 = at * AT;
+      T v[NV];
 #pragma unroll
-        for (int j = 0; j < RC; ++j)
-          if (j < nr) acc[j] = acc[j] + cmulc(w, y[(size_t)(r0 + j) * ystr + (size_t)comp * V + s]);
+      for (int q = 0; q < AT; ++q) {
+        const int a = min(a0 + q, g.ntv - 1);
+        T sc = (act && a0 + q < g.ntv) ? (T)1 : (T)0;
+        if constexpr (is_half<S>()) sc *= (T)bv.Wsc[(size_t)a * V + site];
+        cx<T> wv[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) wv[k] = sc * ldc<T>(bv.W, ((size_t)a * 12 + k) * V + site);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < RT; ++j) {
+            cx<T> acc = mk((T)0, (T)0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc = acc + cmulc(wv[6 * h + k], yv[j][6 * h + k]);
+            const int idx = ((q * 2 + h) * RT + j) * 2;
+            v[idx] = acc.r;
+            v[idx + 1] = acc.i;
+          }
+      }
+      const T mine = reduce_scatter<NV, T>(v, lane);
+      if (lane < NV) red[w][at][lane] = mine;
+    }
+    __syncthreads();
+    for (int e = l; e < nat * NV; e += blockDim.x) {
+      const int at = e / NV, idx = e % NV;
+      T t = (T)0;
+      for (int k = 0; k < nw; ++k) t += red[k][at][idx];
+      // idx = ((q * 2 + h) * RT + j) * 2 + part
+      const int part = idx & 1, j = (idx >> 1) % RT, h = (idx / (2 * RT)) & 1, q = idx / (4 * RT);
+      const int a = at * AT + q;
+      if (a < g.ntv && j < nr) {
+        T* o = reinterpret_cast<T*>(out + (size_t)(r0 + j) * ostr_r + (size_t)ci * ostr_b + h * g.ntv + a);
+        o[part] = t;
       }
     }
-#pragma unroll
-    for (int j = 0; j < RC; ++j) {
-      T re = wave_sum(acc[j].r), im = wave_sum(acc[j].i);
-      if (lane == 0 && j < nr) out[(size_t)(r0 + j) * ostr_r + (size_t)ci * ostr_b + h * g.ntv + a] = mk(re, im);
-    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------- prolongation
-// One thread per (site, rhs): x(site) = sum_a W_a(site) x_c[block, h, a].
+// One workgroup per block, one lane per site; the block's coarse vector of
+// every rhs sits in LDS and is read as a broadcast.
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void prolong_kernel(cx<T>* __restrict__ x, size_t xstr, const cx<T>* __restrict__ xc,
-                                                      size_t cstr, BasisView<S> bv, Geom g,
-                                                      const int* __restrict__ b2i) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.V) return;
-  const int r = blockIdx.y;
+                                                      size_t cstr, BasisView<S> bv, Geom g, int nrhs) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  cx<T>* xl = reinterpret_cast<cx<T>*>(smem_raw);  // [nrhs][nc]
+  const int ci = blockIdx.x;
+  const int l = threadIdx.x;
   const size_t V = g.V;
-  int c[4];
-  site_coords(g, s, c);
-  const int ci = b2i[block_of(g, c)];
-  const cx<T>* xp = xc + (size_t)r * cstr + (size_t)ci * g.nc;
-  cx<T> acc[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = mk((T)0, (T)0);
-  for (int a = 0; a < g.ntv; ++a) {
-    T sc = (T)1;
-    if constexpr (is_half<S>()) sc = (T)bv.Wsc[(size_t)a * V + s];
-    const cx<T> xl = sc * xp[a], xr = sc * xp[g.ntv + a];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      cx<T> w = ldc<T>(bv.W, ((size_t)a * 12 + k) * V + s);
-      acc[k] = acc[k] + w * (k < 6 ? xl : xr);
-    }
+  for (int e = l; e < nrhs * g.nc; e += blockDim.x) {
+    const int r = e / g.nc, k = e % g.nc;
+    xl[e] = xc[(size_t)r * cstr + (size_t)ci * g.nc + k];
   }
+  __syncthreads();
+  if (l >= g.vblock) return;
+  const size_t site = (size_t)ci * g.vblock + l;
+  for (int r0 = 0; r0 < nrhs; r0 += RT) {
+    const int nr = min(RT, nrhs - r0);
+    cx<T> acc[RT][12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) x[(size_t)r * xstr + (size_t)k * V + s] = acc[k];
-}
-
-// ------------------------------------------------------------ D_c stencil
-// One wave per (output coarse site, group of RB right-hand sides); lane =
-// row.  out = add + cs D_self xs + cn sum_{slot>0} D_slot xn(nbr).
-template <typename T, typename S, int RB>
-__global__ __launch_bounds__(64) void coarse_stencil_kernel(cx<T>* __restrict__ out, size_t ostr, int out_first,
-                                                            const cx<T>* __restrict__ add, size_t astr,
-                                                            const cx<T>* __restrict__ xs, size_t xsstr, int xs_first,
-                                                            T cs, const cx<T>* __restrict__ xn, size_t xnstr,
-                                                            int xn_first, T cn, CoarseView<S> cv, int nc, int nrhs) {
-  const int ci = out_first + blockIdx.x;
-  const int r0 = blockIdx.y * RB;
-  const int nr = min(RB, nrhs - r0);
-  const int lane = threadIdx.x;
-  const size_t nn = (size_t)nc * nc;
-  for (int row0 = 0; row0 < nc; row0 += 64) {
-    const int row = row0 + lane;
-    if (row >= nc) break;
-    cx<T> acc[RB];
+    for (int j = 0; j < RT; ++j)
 #pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      acc[j] = mk((T)0, (T)0);
-      if (add && j < nr) acc[j] = add[(size_t)(r0 + j) * astr + (size_t)(ci - out_first) * nc + row];
-    }
-    for (int slot = (cs != (T)0 ? 0 : 1); slot < (cn != (T)0 ? 9 : 1); ++slot) {
-      const int nb = slot == 0 ? ci : cv.nbr[ci * 9 + slot];
-      const cx<T>* xv = slot == 0 ? xs + (size_t)(nb - xs_first) * nc : xn + (size_t)(nb - xn_first) * nc;
-      const size_t xstr = slot == 0 ? xsstr : xnstr;
-      T coef = slot == 0 ? cs : cn;
-      if constexpr (is_half<S>()) coef *= (T)cv.Dsc[ci * 9 + slot];
-      const size_t base = ((size_t)ci * 9 + slot) * nn + row;
-      for (int col = 0; col < nc; ++col) {
-        const cx<T> d = coef * ldc<T>(cv.D, base + (size_t)col * nc);
+      for (int k = 0; k < 12; ++k) acc[j][k] = mk((T)0, (T)0);
+    for (int a = 0; a < g.ntv; ++a) {
+      T sc = (T)1;
+      if constexpr (is_half<S>()) sc = (T)bv.Wsc[(size_t)a * V + site];
+      cx<T> wv[12];
 #pragma unroll
-        for (int j = 0; j < RB; ++j)
-          if (j < nr) acc[j] = acc[j] + d * xv[(size_t)(r0 + j) * xstr + col];
+      for (int k = 0; k < 12; ++k) wv[k] = sc * ldc<T>(bv.W, ((size_t)a * 12 + k) * V + site);
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        if (j >= nr) break;
+        const cx<T> cl = xl[(r0 + j) * g.nc + a], cr = xl[(r0 + j) * g.nc + g.ntv + a];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[j][k] = acc[j][k] + wv[k] * (k < 6 ? cl : cr);
       }
     }
 #pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (j < nr) out[(size_t)(r0 + j) * ostr + (size_t)(ci - out_first) * nc + row] = acc[j];
+    for (int j = 0; j < RT; ++j) {
+      if (j >= nr) break;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) x[(size_t)(r0 + j) * xstr + (size_t)k * V + site] = acc[j][k];
+    }
   }
 }
 
-// out[k] = M[k] x[k], M column-major nc x nc per site
-template <typename T, int RB>
-__global__ __launch_bounds__(64) void block_matvec_kernel(cx<T>* __restrict__ out, size_t ostr,
-                                                          const cx<T>* __restrict__ M, const cx<T>* __restrict__ x,
-                                                          size_t xstr, int nc, int nrhs) {
-  const int k = blockIdx.x;
+// ------------------------------------------------------------ D_c stencil
+// One workgroup per (output coarse site, group of RB right-hand sides).
+// Thread (row, cg) accumulates the columns col = cg (mod CG) of every slot;
+// each slot's input vectors are staged in LDS (read as broadcasts), and the
+// CG partial sums of a row are combined through LDS at the end.
+//   out = add + cs D_self xs + cn sum_{slot>0} D_slot xn(nbr)
+// With Dmat != nullptr the kernel instead computes out = Dmat[k] x[k] for
+// dense column-major per-site matrices (the even-site D_ee^{-1}).
+template <typename T, typename S, int RB>
+__global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__ out, size_t ostr, int out_first,
+                                                             const cx<T>* __restrict__ add, size_t astr,
+                                                             const cx<T>* __restrict__ xs, size_t xsstr, int xs_first,
+                                                             T cs, const cx<T>* __restrict__ xn, size_t xnstr,
+                                                             int xn_first, T cn, CoarseView<S> cv,
+                                                             const cx<T>* __restrict__ Dmat, int nc, int CG,
+                                                             int nrhs) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  cx<T>* xl = reinterpret_cast<cx<T>*>(smem_raw);  // [nc][RB], later [CG][nc][RB]
+  const int ci = out_first + blockIdx.x;
   const int r0 = blockIdx.y * RB;
   const int nr = min(RB, nrhs - r0);
-  const int lane = threadIdx.x;
-  for (int row0 = 0; row0 < nc; row0 += 64) {
-    const int row = row0 + lane;
-    if (row >= nc) break;
-    cx<T> acc[RB];
+  const int t = threadIdx.x;
+  const int row = t % nc, cg = t / nc;
+  const bool act = cg < CG;
+  const size_t nn = (size_t)nc * nc;
+  cx<T> acc[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) acc[j] = mk((T)0, (T)0);
-    const cx<T>* Mk = M + (size_t)k * nc * nc + row;
-    const cx<T>* xk = x + (size_t)k * nc;
-    for (int col = 0; col < nc; ++col) {
-      cx<T> m = Mk[(size_t)col * nc];
-#pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < nr) acc[j] = acc[j] + m * xk[(size_t)(r0 + j) * xstr + col];
+  for (int j = 0; j < RB; ++j) acc[j] = mk((T)0, (T)0);
+  const int s_beg = Dmat ? 0 : (cs != (T)0 ? 0 : 1);
+  const int s_end = Dmat ? 1 : (cn != (T)0 ? 9 : 1);
+  for (int slot = s_beg; slot < s_end; ++slot) {
+    const int nb = slot == 0 ? ci : cv.nbr[ci * 9 + slot];
+    const cx<T>* xv = slot == 0 ? xs + (size_t)(nb - xs_first) * nc : xn + (size_t)(nb - xn_first) * nc;
+    const size_t xstr = slot == 0 ? xsstr : xnstr;
+    T coef = slot == 0 ? cs : cn;
+    if (Dmat) coef = (T)1;
+    if constexpr (is_half<S>()) {
+      if (!Dmat) coef *= (T)cv.Dsc[ci * 9 + slot];
     }
+    __syncthreads();
+    for (int e = t; e < nc * nr; e += blockDim.x) {
+      const int col = e / nr, j = e % nr;
+      xl[col * RB + j] = xv[(size_t)(r0 + j) * xstr + col];
+    }
+    __syncthreads();
+    if (act) {
+      if (Dmat) {
+        const cx<T>* Mk = Dmat + (size_t)(ci - out_first) * nn + row;
+        for (int col = cg; col < nc; col += CG) {
+          const cx<T> d = Mk[(size_t)col * nc];
 #pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (j < nr) out[(size_t)(r0 + j) * ostr + (size_t)k * nc + row] = acc[j];
+          for (int j = 0; j < RB; ++j)
+            if (j < nr) acc[j] = acc[j] + d * xl[col * RB + j];
+        }
+      } else {
+        const size_t base = ((size_t)ci * 9 + slot) * nn + row;
+        for (int col = cg; col < nc; col += CG) {
+          const cx<T> d = coef * ldc<T>(cv.D, base + (size_t)col * nc);
+#pragma unroll
+          for (int j = 0; j < RB; ++j)
+            if (j < nr) acc[j] = acc[j] + d * xl[col * RB + j];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int j = 0; j < RB; ++j) xl[((size_t)cg * nc + row) * RB + j] = acc[j];
+  __syncthreads();
+  for (int e = t; e < nc * nr; e += blockDim.x) {
+    const int rw = e / nr, j = e % nr;
+    cx<T> sum = add ? add[(size_t)(r0 + j) * astr + (size_t)(ci - out_first) * nc + rw] : mk((T)0, (T)0);
+    for (int k = 0; k < CG; ++k) sum = sum + xl[((size_t)k * nc + rw) * RB + j];
+    out[(size_t)(r0 + j) * ostr + (size_t)(ci - out_first) * nc + rw] = sum;
   }
 }
 
@@ -308,9 +407,12 @@ __global__ __launch_bounds__(256) void invert_even_kernel(cx<T>* Dinv, CoarseVie
 
 // ------------------------------------------------------ layout conversion
 template <typename S>
-__global__ void export_coarse_kernel(cx<double>* out, CoarseView<S> cv, int nc, const int* i2b) {
+__global__ void export_coarse_kernel(cx<double>* out, CoarseView<S> cv, Geom g) {
   const int ci = blockIdx.x, slot = blockIdx.y;
-  const int b = i2b[ci];
+  const int nc = g.nc;
+  int bc[4];
+  int_block_coords(g, ci, bc);
+  const int b = lex_block(g, bc);
   const size_t nn = (size_t)nc * nc;
   double sc = 1.0;
   if constexpr (is_half<S>()) sc = (double)cv.Dsc[ci * 9 + slot];
@@ -320,72 +422,97 @@ __global__ void export_coarse_kernel(cx<double>* out, CoarseView<S> cv, int nc, 
   }
 }
 
-template <typename T>
-__global__ void coarse_to_internal_kernel(cx<T>* out, const cx<double>* canon, int nb, int nc, const int* b2i, int nrhs) {
-  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)nrhs * nb * nc) return;
-  const int k = (int)(idx % nc);
-  const size_t rb = idx / nc;
-  const int b = (int)(rb % nb);
-  const int r = (int)(rb / nb);
-  out[((size_t)r * nb + b2i[b]) * nc + k] = cvt<T>(canon[idx]);
+__device__ inline int lex_to_int_block(const Geom& g, int b) {
+  int bc[4];
+  bc[0] = b % g.NB[0]; b /= g.NB[0];
+  bc[1] = b % g.NB[1]; b /= g.NB[1];
+  bc[2] = b % g.NB[2];
+  bc[3] = b / g.NB[2];
+  return block_to_int(g, bc);
 }
 
 template <typename T>
-__global__ void coarse_to_canonical_kernel(cx<double>* canon, const cx<T>* in, int nb, int nc, const int* b2i,
-                                           int nrhs) {
+__global__ void coarse_to_internal_kernel(cx<T>* out, const cx<double>* canon, Geom g, int nrhs) {
+  const int nb = g.nblocks, nc = g.nc;
   size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nrhs * nb * nc) return;
   const int k = (int)(idx % nc);
   const size_t rb = idx / nc;
   const int b = (int)(rb % nb);
-  const int r = (int)(rb / nb);
-  canon[idx] = cvt<double>(in[((size_t)r * nb + b2i[b]) * nc + k]);
+  const size_t r = rb / nb;
+  out[(r * nb + lex_to_int_block(g, b)) * nc + k] = cvt<T>(canon[idx]);
+}
+
+template <typename T>
+__global__ void coarse_to_canonical_kernel(cx<double>* canon, const cx<T>* in, Geom g, int nrhs) {
+  const int nb = g.nblocks, nc = g.nc;
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nrhs * nb * nc) return;
+  const int k = (int)(idx % nc);
+  const size_t rb = idx / nc;
+  const int b = (int)(rb % nb);
+  const size_t r = rb / nb;
+  canon[idx] = cvt<double>(in[(r * nb + lex_to_int_block(g, b)) * nc + k]);
 }
 
 }  // namespace
 
 template <typename T, typename S>
 void launch_restrict(cx<T>* out, size_t ostr_r, size_t ostr_b, const cx<T>* y, size_t ystr, const BasisView<S>& bv,
-                     const Geom& g, const int* b2i, int nrhs, hipStream_t st) {
+                     const Geom& g, int nrhs, hipStream_t st) {
   if (nrhs <= 0) return;
-  dim3 grid(g.nblocks, 2 * g.ntv);
-  restrict_kernel<T, S><<<grid, 64, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, b2i, nrhs);
+  const int threads = ((g.vblock + 63) / 64) * 64;
+  restrict_kernel<T, S><<<g.nblocks, threads, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, nrhs);
 }
 
 template <typename T, typename S>
 void launch_prolong(cx<T>* x, size_t xstr, const cx<T>* xc, size_t cstr, const BasisView<S>& bv, const Geom& g,
-                    const int* b2i, int nrhs, hipStream_t st) {
+                    int nrhs, hipStream_t st) {
   if (nrhs <= 0) return;
-  dim3 grid((g.V + 255) / 256, nrhs);
-  prolong_kernel<T, S><<<grid, 256, 0, st>>>(x, xstr, xc, cstr, bv, g, b2i);
+  const int threads = ((g.vblock + 63) / 64) * 64;
+  const size_t lds = (size_t)nrhs * g.nc * sizeof(cx<T>);
+  prolong_kernel<T, S><<<g.nblocks, threads, lds, st>>>(x, xstr, xc, cstr, bv, g, nrhs);
 }
+
+namespace {
+template <typename T, typename S>
+void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T>* add, size_t astr,
+                    const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr, int xn_first,
+                    T cn, const CoarseView<S>& cv, const cx<T>* Dmat, int nc, int nrhs, hipStream_t st) {
+  if (nrhs <= 0 || nout <= 0) return;
+  const int CG = nc >= 256 ? 1 : 256 / nc;
+  const int threads = CG * nc;
+  if (nrhs == 1) {
+    const size_t lds = (size_t)CG * nc * 1 * sizeof(cx<T>);
+    coarse_stencil_kernel<T, S, 1><<<dim3(nout, 1), threads, lds, st>>>(out, ostr, out_first, add, astr, xs, xsstr,
+                                                                        xs_first, cs, xn, xnstr, xn_first, cn, cv,
+                                                                        Dmat, nc, CG, nrhs);
+  } else if (nrhs <= 4) {
+    const size_t lds = (size_t)CG * nc * 4 * sizeof(cx<T>);
+    coarse_stencil_kernel<T, S, 4><<<dim3(nout, 1), threads, lds, st>>>(out, ostr, out_first, add, astr, xs, xsstr,
+                                                                        xs_first, cs, xn, xnstr, xn_first, cn, cv,
+                                                                        Dmat, nc, CG, nrhs);
+  } else {
+    const size_t lds = (size_t)CG * nc * 12 * sizeof(cx<T>);
+    coarse_stencil_kernel<T, S, 12><<<dim3(nout, (nrhs + 11) / 12), threads, lds, st>>>(
+        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
+  }
+}
+}  // namespace
 
 template <typename T, typename S>
 void launch_coarse_stencil(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T>* add, size_t astr,
                            const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr,
                            int xn_first, T cn, const CoarseView<S>& cv, const Geom& g, int nrhs, hipStream_t st) {
-  if (nrhs <= 0 || nout <= 0) return;
-  if (nrhs == 1) {
-    dim3 grid(nout, 1);
-    coarse_stencil_kernel<T, S, 1><<<grid, 64, 0, st>>>(out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn,
-                                                        xnstr, xn_first, cn, cv, g.nc, nrhs);
-  } else {
-    dim3 grid(nout, (nrhs + 11) / 12);
-    coarse_stencil_kernel<T, S, 12><<<grid, 64, 0, st>>>(out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn,
-                                                         xnstr, xn_first, cn, cv, g.nc, nrhs);
-  }
+  stencil_launch<T, S>(out, ostr, out_first, nout, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv,
+                       nullptr, g.nc, nrhs, st);
 }
 
 template <typename T>
 void launch_block_matvec(cx<T>* out, size_t ostr, const cx<T>* M, const cx<T>* x, size_t xstr, int nsites, int nc,
                          int nrhs, hipStream_t st) {
-  if (nrhs <= 0 || nsites <= 0) return;
-  if (nrhs == 1) {
-    block_matvec_kernel<T, 1><<<dim3(nsites, 1), 64, 0, st>>>(out, ostr, M, x, xstr, nc, nrhs);
-  } else {
-    block_matvec_kernel<T, 12><<<dim3(nsites, (nrhs + 11) / 12), 64, 0, st>>>(out, ostr, M, x, xstr, nc, nrhs);
-  }
+  CoarseView<T> none{nullptr, nullptr, nullptr};
+  stencil_launch<T, T>(out, ostr, 0, nsites, nullptr, 0, x, xstr, 0, (T)1, nullptr, 0, 0, (T)0, none, M, nc, nrhs, st);
 }
 
 template <typename T>
@@ -405,34 +532,32 @@ void launch_invert_even_blocks(cx<T>* Dinv, const CoarseView<S>& cv, const Geom&
 }
 
 template <typename T, typename S>
-void launch_export_coarse(cx<double>* out, const CoarseView<S>& cv, const Geom& g, const int* i2b, hipStream_t st) {
-  export_coarse_kernel<S><<<dim3(g.nblocks, 9), 256, 0, st>>>(out, cv, g.nc, i2b);
+void launch_export_coarse(cx<double>* out, const CoarseView<S>& cv, const Geom& g, hipStream_t st) {
+  export_coarse_kernel<S><<<dim3(g.nblocks, 9), 256, 0, st>>>(out, cv, g);
 }
 
 template <typename T>
-void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, const int* b2i, int nrhs,
-                               hipStream_t st) {
+void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * g.nblocks * g.nc;
-  if (n) coarse_to_internal_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, canon, g.nblocks, g.nc, b2i, nrhs);
+  if (n) coarse_to_internal_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, canon, g, nrhs);
 }
 template <typename T>
-void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, const int* b2i, int nrhs,
-                                hipStream_t st) {
+void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * g.nblocks * g.nc;
-  if (n) coarse_to_canonical_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(canon, in, g.nblocks, g.nc, b2i, nrhs);
+  if (n) coarse_to_canonical_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(canon, in, g, nrhs);
 }
 
 #define INST_TS(T, S)                                                                                               \
   template void launch_restrict<T, S>(cx<T>*, size_t, size_t, const cx<T>*, size_t, const BasisView<S>&,            \
-                                      const Geom&, const int*, int, hipStream_t);                                    \
-  template void launch_prolong<T, S>(cx<T>*, size_t, const cx<T>*, size_t, const BasisView<S>&, const Geom&,         \
-                                     const int*, int, hipStream_t);                                                  \
+                                      const Geom&, int, hipStream_t);                                                \
+  template void launch_prolong<T, S>(cx<T>*, size_t, const cx<T>*, size_t, const BasisView<S>&, const Geom&, int,    \
+                                     hipStream_t);                                                                   \
   template void launch_coarse_stencil<T, S>(cx<T>*, size_t, int, int, const cx<T>*, size_t, const cx<T>*, size_t,    \
                                             int, T, const cx<T>*, size_t, int, T, const CoarseView<S>&, const Geom&, \
                                             int, hipStream_t);                                                       \
   template void launch_quantize_coarse<T, S>(stc_t<S>*, float*, const cx<T>*, const Geom&, hipStream_t);             \
   template void launch_invert_even_blocks<T, S>(cx<T>*, const CoarseView<S>&, const Geom&, int*, hipStream_t);       \
-  template void launch_export_coarse<T, S>(cx<double>*, const CoarseView<S>&, const Geom&, const int*, hipStream_t);
+  template void launch_export_coarse<T, S>(cx<double>*, const CoarseView<S>&, const Geom&, hipStream_t);
 INST_TS(double, double)
 INST_TS(float, float)
 INST_TS(float, __half)
@@ -442,8 +567,8 @@ INST_TS(float, __half)
   template void launch_block_matvec<T>(cx<T>*, size_t, const cx<T>*, const cx<T>*, size_t, int, int, int,            \
                                        hipStream_t);                                                                 \
   template void launch_dagger_fill<T>(cx<T>*, const int*, const Geom&, hipStream_t);                                 \
-  template void launch_coarse_to_internal<T>(cx<T>*, const cx<double>*, const Geom&, const int*, int, hipStream_t);  \
-  template void launch_coarse_to_canonical<T>(cx<double>*, const cx<T>*, const Geom&, const int*, int, hipStream_t);
+  template void launch_coarse_to_internal<T>(cx<T>*, const cx<double>*, const Geom&, int, hipStream_t);              \
+  template void launch_coarse_to_canonical<T>(cx<double>*, const cx<T>*, const Geom&, int, hipStream_t);
 INST_T(double)
 INST_T(float)
 #undef INST_T

@@ -14,6 +14,9 @@
 // Variants: the full operator, the block operator B (hops leaving the block
 // dropped, Alg. 3), and the block-crossing forward/backward hops of one
 // direction (the pieces D_ij of Eq. cgo for a neighbour block j).
+// Workgroups walk the blocks in lexicographic order (through the XCD
+// swizzle), so face neighbours are processed at the same time on the same
+// XCD although blocks of opposite parity are far apart in memory.
 #include "dirac_device.h"
 
 namespace ddamg {
@@ -27,14 +30,20 @@ template <typename Tin, typename Tout, typename S, typename Tc, int MODE>
 __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out, const cx<Tin>* __restrict__ in,
                                                      GaugeView<S> gv, Geom g, int mu_sel, int chi_in, size_t in_rs,
                                                      size_t out_rs) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.V) return;
+  const int ls = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;  // lexicographic-block order
+  if (ls >= g.V) return;
+  const int bl = ls / g.vblock;
+  int bc[4];
+  bc[0] = bl % g.NB[0];
+  bc[1] = (bl / g.NB[0]) % g.NB[1];
+  bc[2] = (bl / (g.NB[0] * g.NB[1])) % g.NB[2];
+  bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
+  const int s = block_to_int(g, bc) * g.vblock + (ls - bl * g.vblock);
   const int r = blockIdx.y;
   const cx<Tin>* ip = in + (size_t)r * in_rs;
   cx<Tout>* op = out + (size_t)r * out_rs;
   const size_t V = g.V;
-  int c[4];
-  site_coords(g, s, c);
+  const SitePos pos = site_pos(g, s);
   cx<Tc> acc[4][3];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -42,13 +51,10 @@ __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out,
     for (int k = 0; k < 3; ++k) acc[sp][k] = mk((Tc)0, (Tc)0);
   if (MODE == DS_FULL || MODE == DS_BLOCK) {
     cx<Tc> p[4][3];
-    load_spinor<Tin, Tc>(p, ip, s, V, chi_in, (Tc)1);
+    load_spinor<Tin, Tc, MODE != DS_FULL>(p, ip, s, V, chi_in, (Tc)1);
     clover_apply<Tc, S>(acc, p, gv, s, V);
   }
-  hops_mu<0, Tin, Tc, S, MODE>(acc, ip, gv, g, c, s, mu_sel, chi_in);
-  hops_mu<1, Tin, Tc, S, MODE>(acc, ip, gv, g, c, s, mu_sel, chi_in);
-  hops_mu<2, Tin, Tc, S, MODE>(acc, ip, gv, g, c, s, mu_sel, chi_in);
-  hops_mu<3, Tin, Tc, S, MODE>(acc, ip, gv, g, c, s, mu_sel, chi_in);
+  hops_all<Tin, Tc, S, MODE>(acc, ip, gv, g, pos, mu_sel, chi_in);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll

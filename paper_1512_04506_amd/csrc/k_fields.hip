@@ -10,11 +10,15 @@ constexpr int TPB = 256;
 
 inline unsigned nblk(size_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
 
-__global__ void gauge_import_kernel(cx<double>* U, const cx<double>* canon, int V) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= V) return;
+__global__ void gauge_import_kernel(cx<double>* U, const cx<double>* canon, Geom g) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  int c[4];
+  site_coords(g, s, c);
+  const size_t lex = lex_site(g, c);
+  const size_t V = g.V;
   for (int mu = 0; mu < 4; ++mu)
-    for (int e = 0; e < 9; ++e) U[((size_t)mu * 9 + e) * V + s] = canon[((size_t)s * 4 + mu) * 9 + e];
+    for (int e = 0; e < 9; ++e) U[((size_t)mu * 9 + e) * V + s] = canon[(lex * 4 + mu) * 9 + e];
 }
 
 struct M3 {
@@ -175,36 +179,45 @@ __global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, S* Aq, float* As
   }
 }
 
+// internal element (r, comp, S) <-> canonical element (r, lex(S), comp)
 template <typename T>
-__global__ void spinor_to_internal_kernel(cx<T>* out, const cx<double>* canon, int V, int nrhs) {
+__global__ void spinor_to_internal_kernel(cx<T>* out, const cx<double>* canon, Geom g, int nrhs) {
+  const size_t V = g.V;
   size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)nrhs * 12 * V;
-  if (idx >= n) return;
-  int s = (int)(idx % V);
-  size_t rc = idx / V;
-  int comp = (int)(rc % 12);
-  int r = (int)(rc / 12);
-  out[idx] = cvt<T>(canon[((size_t)r * V + s) * 12 + comp]);
+  if (idx >= (size_t)nrhs * 12 * V) return;
+  const int s = (int)(idx % V);
+  const size_t rc = idx / V;
+  const int comp = (int)(rc % 12);
+  const size_t r = rc / 12;
+  int c[4];
+  site_coords(g, s, c);
+  out[idx] = cvt<T>(canon[(r * V + lex_site(g, c)) * 12 + comp]);
 }
 
 template <typename T>
-__global__ void spinor_to_canonical_kernel(cx<double>* canon, const cx<T>* in, int V, int nrhs) {
+__global__ void spinor_to_canonical_kernel(cx<double>* canon, const cx<T>* in, Geom g, int nrhs) {
+  const size_t V = g.V;
   size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)nrhs * 12 * V;
-  if (idx >= n) return;
-  int s = (int)(idx % V);
-  size_t rc = idx / V;
-  int comp = (int)(rc % 12);
-  int r = (int)(rc / 12);
-  canon[((size_t)r * V + s) * 12 + comp] = cvt<double>(in[idx]);
+  if (idx >= (size_t)nrhs * 12 * V) return;
+  const int s = (int)(idx % V);
+  const size_t rc = idx / V;
+  const int comp = (int)(rc % 12);
+  const size_t r = rc / 12;
+  int c[4];
+  site_coords(g, s, c);
+  canon[(r * V + lex_site(g, c)) * 12 + comp] = cvt<double>(in[idx]);
 }
 
-__global__ void clover_export_kernel(cx<double>* out, const double* A, int V) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= V) return;
+__global__ void clover_export_kernel(cx<double>* out, const double* A, Geom g) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const size_t V = g.V;
+  int c[4];
+  site_coords(g, s, c);
+  const size_t lex = lex_site(g, c);
   for (int h = 0; h < 2; ++h) {
     const double* Ah = A + (size_t)h * 36 * V;
-    cx<double>* o = out + ((size_t)s * 2 + h) * 36;
+    cx<double>* o = out + (lex * 2 + h) * 36;
     for (int k = 0; k < 6; ++k) o[k * 6 + k] = mk(Ah[(size_t)k * V + s], 0.0);
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
@@ -219,7 +232,7 @@ __global__ void clover_export_kernel(cx<double>* out, const double* A, int V) {
 }  // namespace
 
 void launch_gauge_import(cx<double>* U, const cx<double>* canon, const Geom& g, hipStream_t st) {
-  gauge_import_kernel<<<nblk(g.V), TPB, 0, st>>>(U, canon, g.V);
+  gauge_import_kernel<<<nblk(g.V), TPB, 0, st>>>(U, canon, g);
 }
 
 void launch_clover_build(double* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st) {
@@ -241,12 +254,12 @@ template void launch_quantize_gauge<__half>(stc_t<__half>*, float*, __half*, flo
 template <typename T>
 void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * 12 * g.V;
-  if (n) spinor_to_internal_kernel<T><<<nblk(n), TPB, 0, st>>>(out, canon, g.V, nrhs);
+  if (n) spinor_to_internal_kernel<T><<<nblk(n), TPB, 0, st>>>(out, canon, g, nrhs);
 }
 template <typename T>
 void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * 12 * g.V;
-  if (n) spinor_to_canonical_kernel<T><<<nblk(n), TPB, 0, st>>>(canon, in, g.V, nrhs);
+  if (n) spinor_to_canonical_kernel<T><<<nblk(n), TPB, 0, st>>>(canon, in, g, nrhs);
 }
 template void launch_spinor_to_internal<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
 template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, const Geom&, int, hipStream_t);
@@ -254,7 +267,7 @@ template void launch_spinor_to_canonical<double>(cx<double>*, const cx<double>*,
 template void launch_spinor_to_canonical<float>(cx<double>*, const cx<float>*, const Geom&, int, hipStream_t);
 
 void launch_clover_export(cx<double>* out, const double* A, const Geom& g, hipStream_t st) {
-  clover_export_kernel<<<nblk(g.V), TPB, 0, st>>>(out, A, g.V);
+  clover_export_kernel<<<nblk(g.V), TPB, 0, st>>>(out, A, g);
 }
 
 }  // namespace ddamg

@@ -27,41 +27,40 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
-// in-block hop of direction MU using rho of the neighbouring site from LDS
+// in-block hops of direction MU using rho of the neighbouring sites from LDS
 template <int MU, typename T, typename S>
-__device__ inline void block_hops(cx<T> acc[4][3], const cx<T>* lds, int vb, int l, const int lc[4], const int lstr[4],
-                                  const Geom& g, int s, const int c[4], const GaugeView<S>& gv, size_t V) {
-  cx<T> p[4][3];
-  if (lc[MU] < g.bs[MU] - 1) {
-    int ln = l + lstr[MU];
+__device__ inline void block_hops(cx<T> acc[4][3], const cx<T>* lds, int vb, const SitePos& p, const Geom& g,
+                                  const GaugeView<S>& gv, size_t V) {
+  cx<T> q[4][3];
+  if (p.lc[MU] < g.bs[MU] - 1) {
+    const int ln = p.l + g.lstr[MU];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) p[sp][k] = lds[(3 * sp + k) * vb + ln];
-    hop_spinor<MU, true, T, S>(acc, p, gv, s, V);
+      for (int k = 0; k < 3; ++k) q[sp][k] = lds[(3 * sp + k) * vb + ln];
+    hop_spinor<MU, true, T, S>(acc, q, gv, p.S, V);
   }
-  if (lc[MU] > 0) {
-    int ln = l - lstr[MU];
+  if (p.lc[MU] > 0) {
+    const int ln = p.l - g.lstr[MU];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) p[sp][k] = lds[(3 * sp + k) * vb + ln];
-    int e[4] = {c[0], c[1], c[2], c[3]};
-    e[MU] -= 1;  // inside the block: no wrap
-    hop_spinor<MU, false, T, S>(acc, p, gv, site_index(g, e), V);
+      for (int k = 0; k < 3; ++k) q[sp][k] = lds[(3 * sp + k) * vb + ln];
+    hop_spinor<MU, false, T, S>(acc, q, gv, p.S - g.lstr[MU], V);
   }
 }
 
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, const cx<T>* __restrict__ y,
-                                                        GaugeView<S> gv, Geom g, const int* __restrict__ colour_blocks,
-                                                        int colour, int n_mr, size_t rs) {
+                                                        GaugeView<S> gv, Geom g, int colour, int n_mr, size_t rs) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   const int vb = g.vblock;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);          // [12][vb]
   T* red = reinterpret_cast<T*>(lds + 12 * vb);               // [nwaves][3]
   const int nwaves = (blockDim.x + 63) / 64;
-  const int b = colour_blocks[colour * (g.nblocks / 2) + blockIdx.x];
+  // blocks of one colour are contiguous; the swizzle gives each XCD one
+  // contiguous run of them (a compact lattice region and its halo)
+  const int ci = colour * g.neven + xcd_swizzle(blockIdx.x, gridDim.x);
   const int r = blockIdx.y;
   const int l = threadIdx.x;
   const bool act = l < vb;
@@ -69,9 +68,8 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
   x += (size_t)r * rs;
   y += (size_t)r * rs;
 
-  int c[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
-  int s = 0;
-  const int lstr[4] = {1, g.bs[0], g.bs[0] * g.bs[1], g.bs[0] * g.bs[1] * g.bs[2]};
+  const int s = ci * vb + (act ? l : 0);
+  const SitePos pos = site_pos(g, s);
   cx<T> rho[4][3], e[4][3];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -81,12 +79,6 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
       e[sp][k] = mk((T)0, (T)0);
     }
   if (act) {
-    s = block_site(g, b, l, c);
-    int t = l;
-    lc[0] = t % g.bs[0]; t /= g.bs[0];
-    lc[1] = t % g.bs[1]; t /= g.bs[1];
-    lc[2] = t % g.bs[2];
-    lc[3] = t / g.bs[2];
     // residual r = y - D x with the current x (global memory)
     cx<T> acc[4][3];
 #pragma unroll
@@ -94,12 +86,9 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
 #pragma unroll
       for (int k = 0; k < 3; ++k) acc[sp][k] = mk((T)0, (T)0);
     cx<T> p[4][3];
-    load_spinor<T, T>(p, x, s, V, -1, (T)1);
+    load_spinor<T, T, false>(p, x, s, V, -1, (T)1);
     clover_apply<T, S>(acc, p, gv, s, V);
-    hops_mu<0, T, T, S, DS_FULL>(acc, x, gv, g, c, s, 0, -1);
-    hops_mu<1, T, T, S, DS_FULL>(acc, x, gv, g, c, s, 0, -1);
-    hops_mu<2, T, T, S, DS_FULL>(acc, x, gv, g, c, s, 0, -1);
-    hops_mu<3, T, T, S, DS_FULL>(acc, x, gv, g, c, s, 0, -1);
+    hops_all<T, T, S, DS_FULL>(acc, x, gv, g, pos, 0, -1);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -107,6 +96,11 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
   }
 
   for (int it = 0; it < n_mr; ++it) {
+    // Launder the link/clover pointers: the loads of B below are the same in
+    // every MR step, and hoisting them out of the loop would pin ~200 values
+    // in registers for the whole kernel.
+    GaugeView<S> gvi = gv;
+    asm volatile("" : "+s"(gvi.U), "+s"(gvi.A));
     if (act) {
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
@@ -121,11 +115,11 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
       for (int k = 0; k < 3; ++k) q[sp][k] = mk((T)0, (T)0);
     T qr_re = 0, qr_im = 0, qq = 0;
     if (act) {
-      clover_apply<T, S>(q, rho, gv, s, V);
-      block_hops<0, T, S>(q, lds, vb, l, lc, lstr, g, s, c, gv, V);
-      block_hops<1, T, S>(q, lds, vb, l, lc, lstr, g, s, c, gv, V);
-      block_hops<2, T, S>(q, lds, vb, l, lc, lstr, g, s, c, gv, V);
-      block_hops<3, T, S>(q, lds, vb, l, lc, lstr, g, s, c, gv, V);
+      clover_apply<T, S>(q, rho, gvi, s, V);
+      block_hops<0, T, S>(q, lds, vb, pos, g, gvi, V);
+      block_hops<1, T, S>(q, lds, vb, pos, g, gvi, V);
+      block_hops<2, T, S>(q, lds, vb, pos, g, gvi, V);
+      block_hops<3, T, S>(q, lds, vb, pos, g, gvi, V);
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -177,21 +171,21 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
 }  // namespace
 
 template <typename T, typename S>
-void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, const int* colour_blocks,
-                      int colour, int n_mr, int nrhs, hipStream_t st) {
+void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, int colour, int n_mr, int nrhs,
+                      hipStream_t st) {
   if (nrhs <= 0) return;
   int threads = ((g.vblock + 63) / 64) * 64;
   int nwaves = threads / 64;
   size_t lds = (size_t)12 * g.vblock * sizeof(cx<T>) + (size_t)3 * nwaves * sizeof(T);
   dim3 grid(g.nblocks / 2, nrhs);
-  sap_phase_kernel<T, S><<<grid, threads, lds, st>>>(x, y, gv, g, colour_blocks, colour, n_mr, (size_t)12 * g.V);
+  sap_phase_kernel<T, S><<<grid, threads, lds, st>>>(x, y, gv, g, colour, n_mr, (size_t)12 * g.V);
 }
 
 template void launch_sap_phase<double, double>(cx<double>*, const cx<double>*, const GaugeView<double>&, const Geom&,
-                                               const int*, int, int, int, hipStream_t);
+                                               int, int, int, hipStream_t);
 template void launch_sap_phase<float, float>(cx<float>*, const cx<float>*, const GaugeView<float>&, const Geom&,
-                                             const int*, int, int, int, hipStream_t);
+                                             int, int, int, hipStream_t);
 template void launch_sap_phase<float, __half>(cx<float>*, const cx<float>*, const GaugeView<__half>&, const Geom&,
-                                              const int*, int, int, int, hipStream_t);
+                                              int, int, int, hipStream_t);
 
 }  // namespace ddamg

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W,
   __shared__ cx<double> G[MAX_NTV][MAX_NTV];
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];  // T^{-1}, upper triangular
   __shared__ int fail;
-  const int b = blockIdx.x >> 1;
+  const int ci = blockIdx.x >> 1;  // internal block: its sites are ci * vblock + [0, vblock)
   const int h = blockIdx.x & 1;
   const int n = g.ntv;
   const int npairs = n * (n + 1) / 2;
@@ -57,8 +57,7 @@ __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W,
         const int a = e % n;
         const int rk = e / n;  // row in chunk = site_local * 6 + k
         const int k = rk % 6;
-        int c[4];
-        const int s = block_site(g, b, l0 + rk / 6, c);
+        const int s = ci * g.vblock + l0 + rk / 6;
         L[rk][a] = W[((size_t)a * 12 + 6 * h + k) * V + s];
       }
       __syncthreads();
@@ -115,8 +114,7 @@ __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W,
     // X <- X T^{-1}, one row per thread iteration
     for (int row = tid; row < 6 * g.vblock; row += QR_THREADS) {
       const int k = row % 6;
-      int c[4];
-      const int s = block_site(g, b, row / 6, c);
+      const int s = ci * g.vblock + row / 6;
       cx<double> x[MAX_NTV];
       for (int a = 0; a < n; ++a) x[a] = W[((size_t)a * 12 + 6 * h + k) * V + s];
       for (int j = n - 1; j >= 0; --j) {

@@ -1,0 +1,97 @@
+"""The C ABI library loads, exports every entry point declared in
+include/ddamg.h, and validates arguments before any HIP call (no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddamg.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_1512_04506_amd as dd
+    return dd
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for n in ("mg_setup", "mg_apply", "dirac_apply", "coarse_apply", "solve", "ddamg_create", "ddamg_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(dd):
+    names = _declared_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", dd.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if " T " in line)
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n)
+    assert set(dd.EXPORTS) == set(names)
+
+
+def test_default_params(dd):
+    p = dd.default_params()
+    assert tuple(p.block) == (4, 4, 4, 4)
+    assert p.ntv == 24 and p.nu == 3 and p.n_mr == 4 and p.n_setup == 3
+    assert p.coarse_tol == 0.05 and p.coarse_restart == 30 and p.coarse_maxit == 300
+    assert p.outer_restart == 20 and p.prec == dd.MIXED16 and p.max_rhs == 12
+    assert dd.validate_params(p) == (0, "")
+
+
+@pytest.mark.parametrize("change,needle", [
+    (dict(block=(3, 4, 4, 4)), "divide"),
+    (dict(L=(12, 8, 8, 8)), "even"),
+    (dict(L=(8, 8, 8, 4), block=(4, 4, 4, 4)), "even"),
+    (dict(block=(1, 1, 1, 1), L=(8, 8, 8, 8), ntv=8), "aggregates too small"),
+    (dict(ntv=0), "ntv"),
+    (dict(ntv=33), "ntv"),
+    (dict(prec=7), "precision"),
+    (dict(max_rhs=0), "max_rhs"),
+    (dict(max_rhs=65), "max_rhs"),
+    (dict(coarse_restart=0), "restart"),
+    (dict(outer_restart=65), "restart"),
+    (dict(coarse_tol=0.0), "coarse_tol"),
+    (dict(nu=-1), "non-negative"),
+    (dict(L=(16, 16, 16, 16), block=(8, 8, 4, 2)), "256"),
+    (dict(m0=float("nan")), "finite"),
+])
+def test_validation_rejects(dd, change, needle):
+    p = dd.default_params(**change)
+    rc, msg = dd.validate_params(p)
+    assert rc == -1
+    assert needle in msg
+
+
+def test_create_rejects_before_any_hip_call(dd):
+    """Invalid parameters and NULL pointers come back as codes on a machine
+    without a GPU, i.e. before the HIP runtime is touched."""
+    lib = dd.lib
+    h = ctypes.c_void_p()
+    p = dd.default_params(block=(3, 4, 4, 4))
+    rc = lib.ddamg_create(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert b"divide" in lib.ddamg_last_error(None)
+    p = dd.default_params()
+    rc = lib.ddamg_create(ctypes.byref(p), None, None, ctypes.byref(h))
+    assert rc == -1
+    assert b"gauge" in lib.ddamg_last_error(None)
+    assert lib.ddamg_destroy(None) == -1
+    assert lib.mg_setup(None, None) == -1
+    assert lib.solve(None, None, None, 1, 1e-10, None) == -1
+    assert lib.dirac_apply(None, None, None, 1, 0) == -1
+    assert lib.coarse_apply(None, None, None, 1) == -1
+    assert lib.mg_apply(None, None, None, 1) == -1
+    assert lib.ddamg_volume(None) == -1

@@ -162,7 +162,7 @@ struct ddamg_ctx {
   DevBuf status;
   int* h_flags = nullptr;        // pinned host mirrors of small device arrays
   double* h_dbl = nullptr;       // [128]
-  cx<double>* h_cx = nullptr;    // [64]
+  cx<double>* h_cx = nullptr;    // [128]
   // canonical <-> internal staging
   DevBuf stage_in, stage_out;
   size_t stage_rhs = 0;
@@ -171,10 +171,10 @@ struct ddamg_ctx {
   bool setup_done = false;
   ddamg_stats stats{};
 
-  GaugeView<double> gv64() const { return {U64.get<cx<double>>(), nullptr, A64.get<double>(), nullptr}; }
-  GaugeView<float> gv32() const { return {U32.get<cx<float>>(), nullptr, A32.get<float>(), nullptr}; }
+  GaugeView<double> gv64() const { return {U64.get<cx<double>>(), nullptr, A64.get<cx<double>>(), nullptr}; }
+  GaugeView<float> gv32() const { return {U32.get<cx<float>>(), nullptr, A32.get<cx<float>>(), nullptr}; }
   GaugeView<__half> gvh() const {
-    return {Uh.get<__half2>(), Uhs.get<float>(), Ah.get<__half>(), Ahs.get<float>()};
+    return {Uh.get<__half2>(), Uhs.get<float>(), Ah.get<__half2>(), Ahs.get<float>()};
   }
   void ensure_stage(int nrhs) {
     if ((size_t)nrhs <= stage_rhs) return;
@@ -190,6 +190,12 @@ struct ddamg_ctx {
   template <typename F>
   void timed(int kind, int nrhs, F&& f) {
     kt.run(kind, nrhs, st, f);
+  }
+  template <typename F>
+  auto timed_ret(int kind, int nrhs, F&& f) -> decltype(f()) {
+    decltype(f()) r{};
+    kt.run(kind, nrhs, st, [&] { r = f(); });
+    return r;
   }
   void free_pinned() {
     if (h_flags) (void)hipHostFree(h_flags);
@@ -599,6 +605,38 @@ struct Solver final : SolverBase {
   }
 
   // ------------------------------------------------------- outer FGMRES
+  // Classical Gram-Schmidt of w = V_{k+1} against V_0..V_k with selective
+  // re-orthogonalisation: one multi-dot gives V^H w and |w|^2 together (w is
+  // the next basis slot), and a second pass runs only if some rhs lost more
+  // than half of |w|^2 in the projection (norm ratio below 1/sqrt 2), the
+  // criterion of Daniel, Gragg, Kaufman and Stewart.  Returns whether the
+  // second pass ran (its coefficients are then in h2).
+  bool cgs_dgks(cx<double>* V, size_t vsj, int k, int nrhs) {
+    const size_t n = fsz();
+    const int* act = ok.active.get<int>();
+    cx<double>* w = V + (size_t)(k + 1) * vsj;
+    launch_mdot<double>(ok.h1.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 2, w, n, n, nrhs,
+                        act, st);
+    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h1.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
+    launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), w, 0, n, 1, w, n, n, nrhs, act, st);
+    // decide on the host: |w|^2 before (h1[k+1]) and after (n2), active rhs
+    HIPCK(hipMemcpy2DAsync(c->h_cx, sizeof(cx<double>), ok.h1.get<cx<double>>() + (k + 1),
+                           sizeof(cx<double>) * ok.ldh, sizeof(cx<double>), nrhs, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(c->h_cx + 64, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost,
+                         st));
+    HIPCK(hipMemcpyAsync(c->h_flags, act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    c->sync();
+    bool again = false;
+    for (int r = 0; r < nrhs; ++r)
+      if (c->h_flags[r] && c->h_cx[64 + r].r < 0.5 * c->h_cx[r].r) again = true;
+    if (!again) return false;
+    launch_mdot<double>(ok.h2.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 1, w, n, n, nrhs,
+                        act, st);
+    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h2.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
+    launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), w, 0, n, 1, w, n, n, nrhs, act, st);
+    return true;
+  }
+
   void ensure_outer(int m, int nrhs) {
     if (m == outer_m && nrhs <= outer_r) return;
     outer_m = m;
@@ -689,8 +727,8 @@ struct Solver final : SolverBase {
           else
             launch_dslash<float, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
         });
-        c->timed(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { cgs2(ok, V, vsj, n, k, wk, n, n, nrhs); });
-        launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), ok.h2.get<cx<double>>(), ok.ldh,
+        const bool second = c->timed_ret(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { return cgs_dgks(V, vsj, k, nrhs); });
+        launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), second ? ok.h2.get<cx<double>>() : nullptr, ok.ldh,
                               ok.n2.get<cx<double>>(), 1, nrhs, st);
         launch_scale<double, double>(wk, n, wk, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
         ++its;
@@ -888,23 +926,23 @@ int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg
     build_tables(c.get());
     HIPCK(hipHostMalloc((void**)&c->h_flags, 64 * sizeof(int), hipHostMallocDefault));
     HIPCK(hipHostMalloc((void**)&c->h_dbl, 128 * sizeof(double), hipHostMallocDefault));
-    HIPCK(hipHostMalloc((void**)&c->h_cx, 64 * sizeof(cx<double>), hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void**)&c->h_cx, 128 * sizeof(cx<double>), hipHostMallocDefault));
     c->status.alloc<int>(1);
     const size_t V = g.V;
     c->U64.alloc<cx<double>>(36 * V);
-    c->A64.alloc<double>(72 * V);
+    c->A64.alloc<cx<double>>(2 * CLOVER_PAIRS * V);
     c->U32.alloc<cx<float>>(36 * V);
-    c->A32.alloc<float>(72 * V);
+    c->A32.alloc<cx<float>>(2 * CLOVER_PAIRS * V);
     c->Uh.alloc<__half2>(36 * V);
     c->Uhs.alloc<float>(V);
-    c->Ah.alloc<__half>(72 * V);
+    c->Ah.alloc<__half2>(2 * CLOVER_PAIRS * V);
     c->Ahs.alloc<float>(V);
     launch_gauge_import(c->U64.get<cx<double>>(), reinterpret_cast<const cx<double>*>(gauge), g, c->st);
-    launch_clover_build(c->A64.get<double>(), c->U64.get<cx<double>>(), g, p->m0, p->csw, c->st);
-    launch_quantize_gauge<float>(c->U32.get<cx<float>>(), nullptr, c->A32.get<float>(), nullptr,
-                                 c->U64.get<cx<double>>(), c->A64.get<double>(), g, c->st);
-    launch_quantize_gauge<__half>(c->Uh.get<__half2>(), c->Uhs.get<float>(), c->Ah.get<__half>(), c->Ahs.get<float>(),
-                                  c->U64.get<cx<double>>(), c->A64.get<double>(), g, c->st);
+    launch_clover_build(c->A64.get<cx<double>>(), c->U64.get<cx<double>>(), g, p->m0, p->csw, c->st);
+    launch_quantize_gauge<float>(c->U32.get<cx<float>>(), nullptr, c->A32.get<cx<float>>(), nullptr,
+                                 c->U64.get<cx<double>>(), c->A64.get<cx<double>>(), g, c->st);
+    launch_quantize_gauge<__half>(c->Uh.get<__half2>(), c->Uhs.get<float>(), c->Ah.get<__half2>(),
+                                  c->Ahs.get<float>(), c->U64.get<cx<double>>(), c->A64.get<cx<double>>(), g, c->st);
     check_launch("create");
     switch (p->prec) {
       case DDAMG_FP64:
@@ -1028,7 +1066,7 @@ int ddamg_export_coarse(ddamg_ctx* c, double* Dc) {
 int ddamg_export_clover(ddamg_ctx* c, double* A) {
   if (!c || !A) return DDAMG_EARG;
   GUARD_BEGIN
-  launch_clover_export(reinterpret_cast<cx<double>*>(A), c->A64.get<double>(), c->g, c->st);
+  launch_clover_export(reinterpret_cast<cx<double>*>(A), c->A64.get<cx<double>>(), c->g, c->st);
   check_launch("export clover");
   c->sync();
   return DDAMG_OK;

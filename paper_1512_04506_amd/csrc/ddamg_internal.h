@@ -35,6 +35,23 @@ template <typename T>
 __host__ __device__ inline cx<T> cmulc(cx<T> a, cx<T> b) {
   return mk(a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r);
 }
+// acc + a * b and acc + conj(a) * b with four fused multiply-adds each
+template <typename T>
+__host__ __device__ inline cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+  acc.r = fma(a.r, b.r, acc.r);
+  acc.r = fma(-a.i, b.i, acc.r);
+  acc.i = fma(a.r, b.i, acc.i);
+  acc.i = fma(a.i, b.r, acc.i);
+  return acc;
+}
+template <typename T>
+__host__ __device__ inline cx<T> cfmac(cx<T> a, cx<T> b, cx<T> acc) {
+  acc.r = fma(a.r, b.r, acc.r);
+  acc.r = fma(a.i, b.i, acc.r);
+  acc.i = fma(a.r, b.i, acc.i);
+  acc.i = fma(-a.i, b.r, acc.i);
+  return acc;
+}
 template <typename T>
 __host__ __device__ inline cx<T> times_i(cx<T> a) { return mk(-a.i, a.r); }
 template <typename T>
@@ -157,14 +174,17 @@ __host__ __device__ inline int lex_site(const Geom& g, const int c[4]) {
   return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }
 
-// Links [mu][9][V] (row-major 3x3 per link), clover [2][36][V]: per chirality
-// 6 real diagonal entries then the 15 upper off-diagonal entries (i < j,
-// row-major) as (re, im) pairs; row/col index = 3 * spin_in_chirality + colour.
+// Links [mu][9][V] (row-major 3x3 per link), clover [2][18][V] pairs: per
+// chirality the 6 real diagonal entries as 3 pairs (d0, d1), (d2, d3),
+// (d4, d5), then the 15 upper off-diagonal entries (i < j, row-major) as
+// (re, im); row/col index = 3 * spin_in_chirality + colour.  Pairs are
+// loaded as one 4/8/16-byte word.
+constexpr int CLOVER_PAIRS = 18;
 template <typename S>
 struct GaugeView {
   const stc_t<S>* U;
   const float* Usc;   // [V] link scale (half only)
-  const S* A;
+  const stc_t<S>* A;
   const float* Asc;   // [V] clover scale (half only)
 };
 
@@ -191,15 +211,15 @@ enum { DS_FULL = 0, DS_BLOCK = 1, DS_CROSS_FWD = 2, DS_CROSS_BWD = 3 };
 // ---------------------------------------------------------------- launchers
 // fields
 void launch_gauge_import(cx<double>* U, const cx<double>* canon, const Geom& g, hipStream_t st);
-void launch_clover_build(double* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st);
+void launch_clover_build(cx<double>* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st);
 template <typename S>
-void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, S* Aq, float* Asc, const cx<double>* U, const double* A,
-                           const Geom& g, hipStream_t st);
+void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, stc_t<S>* Aq, float* Asc, const cx<double>* U,
+                           const cx<double>* A, const Geom& g, hipStream_t st);
 template <typename T>
 void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st);
 template <typename T>
 void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st);
-void launch_clover_export(cx<double>* out, const double* A, const Geom& g, hipStream_t st);
+void launch_clover_export(cx<double>* out, const cx<double>* A, const Geom& g, hipStream_t st);
 
 // dslash: out[r] = piece of D applied to in[r] (chi_in >= 0 keeps only that
 // chirality of the input; mu selects the direction of the cross variants).

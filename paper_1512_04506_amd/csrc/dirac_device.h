@@ -83,14 +83,14 @@ __device__ inline void load_spinor(cx<Tc> p[4][3], const cx<Tin>* in, int s, siz
   }
 }
 
+// link entries as stored (FP16: without the per-site scale, which the hop
+// applies once to its 2-spinor result)
 template <typename Tc, typename S>
 __device__ inline void load_link(cx<Tc> u[3][3], const GaugeView<S>& gv, int mu, int s, size_t V) {
-  Tc sc = (Tc)1;
-  if constexpr (is_half<S>()) sc = (Tc)gv.Usc[s];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[a][b] = sc * ldc<Tc>(gv.U, (size_t)(mu * 9 + 3 * a + b) * V + s);
+    for (int b = 0; b < 3; ++b) u[a][b] = ldc<Tc>(gv.U, (size_t)(mu * 9 + 3 * a + b) * V + s);
 }
 
 // acc += -1/2 (1 -+ g_mu) [U_mu(slink) or U_mu(slink)^dag] p
@@ -101,16 +101,43 @@ __device__ inline void hop_spinor(cx<Tc> acc[4][3], const cx<Tc> p[4][3], const 
   project<MU, FWD, Tc>(h, p);
   cx<Tc> U[3][3];
   load_link<Tc, S>(U, gv, MU, slink, V);
+  Tc coef = (Tc)-0.5;
+  if constexpr (is_half<S>()) coef *= (Tc)gv.Usc[slink];
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       cx<Tc> t = mk((Tc)0, (Tc)0);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) t = FWD ? t + U[a][b] * h.h[sp][b] : t + cmulc(U[b][a], h.h[sp][b]);
+      for (int b = 0; b < 3; ++b) t = FWD ? cfma(U[a][b], h.h[sp][b], t) : cfmac(U[b][a], h.h[sp][b], t);
       u.h[sp][a] = t;
     }
-  reconstruct<MU, FWD, Tc>(acc, u, (Tc)-0.5);
+  reconstruct<MU, FWD, Tc>(acc, u, coef);
+}
+
+// The same hop applied to NR spinors with one load of the link.
+template <int MU, bool FWD, int NR, typename Tc, typename S>
+__device__ inline void hop_spinor_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const GaugeView<S>& gv,
+                                        int slink, size_t V) {
+  cx<Tc> U[3][3];
+  load_link<Tc, S>(U, gv, MU, slink, V);
+  Tc coef = (Tc)-0.5;
+  if constexpr (is_half<S>()) coef *= (Tc)gv.Usc[slink];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    Half2<Tc> h, u;
+    project<MU, FWD, Tc>(h, p[r]);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cx<Tc> t = mk((Tc)0, (Tc)0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t = FWD ? cfma(U[a][b], h.h[sp][b], t) : cfmac(U[b][a], h.h[sp][b], t);
+        u.h[sp][a] = t;
+      }
+    reconstruct<MU, FWD, Tc>(acc[r], u, coef);
+  }
 }
 
 template <int MU, bool FWD, typename Tin, typename Tc, typename S, bool CHI>
@@ -128,25 +155,66 @@ __device__ inline void clover_apply(cx<Tc> acc[4][3], const cx<Tc> p[4][3], cons
   if constexpr (is_half<S>()) sc = (Tc)gv.Asc[s];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const S* Ah = gv.A + (size_t)h * 36 * V;
+    const stc_t<S>* Ah = gv.A + (size_t)h * CLOVER_PAIRS * V;
     cx<Tc> v[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = p[2 * h + k / 3][k % 3];
     cx<Tc> o[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) o[k] = (sc * ldr<Tc>(Ah, (size_t)k * V + s)) * v[k];
+    for (int k = 0; k < 3; ++k) {
+      const cx<Tc> d = ldc<Tc>(Ah, (size_t)k * V + s);
+      o[2 * k] = d.r * v[2 * k];
+      o[2 * k + 1] = d.i * v[2 * k + 1];
+    }
     int q = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = i + 1; j < 6; ++j) {
-        cx<Tc> a = mk(sc * ldr<Tc>(Ah, (size_t)(6 + 2 * q) * V + s), sc * ldr<Tc>(Ah, (size_t)(7 + 2 * q) * V + s));
-        o[i] = o[i] + a * v[j];
-        o[j] = o[j] + cmulc(a, v[i]);
+        const cx<Tc> a = ldc<Tc>(Ah, (size_t)(3 + q) * V + s);
+        o[i] = cfma(a, v[j], o[i]);
+        o[j] = cfmac(a, v[i], o[j]);
         ++q;
       }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) acc[2 * h + k / 3][k % 3] = acc[2 * h + k / 3][k % 3] + o[k];
+    for (int k = 0; k < 6; ++k) acc[2 * h + k / 3][k % 3] = acc[2 * h + k / 3][k % 3] + sc * o[k];
+  }
+}
+
+// acc[r] += A(x) p[r] for NR spinors with one load of the clover entries
+template <int NR, typename Tc, typename S>
+__device__ inline void clover_apply_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const GaugeView<S>& gv,
+                                          int s, size_t V) {
+  Tc sc = (Tc)1;
+  if constexpr (is_half<S>()) sc = (Tc)gv.Asc[s];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const stc_t<S>* Ah = gv.A + (size_t)h * CLOVER_PAIRS * V;
+    cx<Tc> a[CLOVER_PAIRS];
+#pragma unroll
+    for (int e = 0; e < CLOVER_PAIRS; ++e) a[e] = ldc<Tc>(Ah, (size_t)e * V + s);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      cx<Tc> v[6], o[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] = p[r][2 * h + k / 3][k % 3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        o[2 * k] = a[k].r * v[2 * k];
+        o[2 * k + 1] = a[k].i * v[2 * k + 1];
+      }
+      int q = 0;
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+          o[i] = cfma(a[3 + q], v[j], o[i]);
+          o[j] = cfmac(a[3 + q], v[i], o[j]);
+          ++q;
+        }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[r][2 * h + k / 3][k % 3] = acc[r][2 * h + k / 3][k % 3] + sc * o[k];
+    }
   }
 }
 

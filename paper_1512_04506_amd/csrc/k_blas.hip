@@ -14,6 +14,7 @@ namespace {
 
 constexpr int BT = 256;
 constexpr int JG = 8;  // basis vectors per pass over the chunk
+constexpr int MAX_MDOT_VECS = 66;  // restart length 64 plus w itself
 
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -26,7 +27,7 @@ __global__ __launch_bounds__(BT) void mdot_partial_kernel(cx<double>* part, cons
                                                           size_t vsj, size_t vsr, int nvec,
                                                           const cx<T>* __restrict__ w, size_t wsr, size_t n,
                                                           size_t chunk, int nchunk, const int* active) {
-  __shared__ cx<double> red[64][BT / 64];
+  __shared__ cx<double> red[MAX_MDOT_VECS][BT / 64];
   const int c = blockIdx.x;
   const int r = blockIdx.y;
   if (active && !active[r]) return;
@@ -267,7 +268,7 @@ int blas_nchunks(size_t n) {
 template <typename T>
 void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size_t vsj, size_t vsr, int nvec,
                  const cx<T>* w, size_t wsr, size_t n, int nrhs, const int* active, hipStream_t st) {
-  if (nrhs <= 0 || nvec <= 0) return;
+  if (nrhs <= 0 || nvec <= 0 || nvec > MAX_MDOT_VECS) return;
   const int nchunk = blas_nchunks(n);
   const size_t chunk = (n + nchunk - 1) / nchunk;
   mdot_partial_kernel<T><<<dim3(nchunk, nrhs), BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, n, chunk, nchunk,

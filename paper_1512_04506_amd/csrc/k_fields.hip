@@ -101,7 +101,7 @@ __device__ inline int upper_index(int i, int j) {  // i < j
 //   right block: B1 = F03 - F12, B2 = F02 + F13, B3 = F23 - F01
 // (sigma_{k4} = diag(-s_k, s_k), sigma_{jk} = -eps_{jkl} diag(s_l, s_l)),
 // and A^h = (4 + m0) + c_sw (i/2) sum_l s_l (x) B_l.
-__global__ void clover_kernel(double* A, const cx<double>* U, Geom g, double m0, double csw) {
+__global__ void clover_kernel(cx<double>* A, const cx<double>* U, Geom g, double m0, double csw) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   int c[4];
@@ -141,20 +141,16 @@ __global__ void clover_kernel(double* A, const cx<double>* U, Geom g, double m0,
         full[3 + i][j] = f * times_i(m10);
         full[3 + i][3 + j] = f * times_i(m11);
       }
-    double* Ah = A + (size_t)h * 36 * V;
-    for (int k = 0; k < 6; ++k) Ah[(size_t)k * V + s] = 4.0 + m0 + full[k][k].r;
+    cx<double>* Ah = A + (size_t)h * CLOVER_PAIRS * V;
+    for (int k = 0; k < 3; ++k) Ah[(size_t)k * V + s] = mk(4.0 + m0 + full[2 * k][2 * k].r, 4.0 + m0 + full[2 * k + 1][2 * k + 1].r);
     for (int i = 0; i < 6; ++i)
-      for (int j = i + 1; j < 6; ++j) {
-        int p = upper_index(i, j);
-        Ah[(size_t)(6 + 2 * p) * V + s] = full[i][j].r;
-        Ah[(size_t)(7 + 2 * p) * V + s] = full[i][j].i;
-      }
+      for (int j = i + 1; j < 6; ++j) Ah[(size_t)(3 + upper_index(i, j)) * V + s] = full[i][j];
   }
 }
 
 template <typename S>
-__global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, S* Aq, float* Asc, const cx<double>* U,
-                                      const double* A, int V) {
+__global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, stc_t<S>* Aq, float* Asc, const cx<double>* U,
+                                      const cx<double>* A, int V) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= V) return;
   if constexpr (is_half<S>()) {
@@ -163,7 +159,10 @@ __global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, S* Aq, float* As
       cx<double> u = U[(size_t)e * V + s];
       mu = fmax(mu, fmax(fabs(u.r), fabs(u.i)));
     }
-    for (int e = 0; e < 72; ++e) ma = fmax(ma, fabs(A[(size_t)e * V + s]));
+    for (int e = 0; e < 2 * CLOVER_PAIRS; ++e) {
+      cx<double> a = A[(size_t)e * V + s];
+      ma = fmax(ma, fmax(fabs(a.r), fabs(a.i)));
+    }
     float fu = (float)mu, fa = (float)ma;
     double iu = fu > 0.f ? 1.0 / (double)fu : 0.0, ia = fa > 0.f ? 1.0 / (double)fa : 0.0;
     Usc[s] = fu;
@@ -172,10 +171,13 @@ __global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, S* Aq, float* As
       cx<double> u = U[(size_t)e * V + s];
       Uq[(size_t)e * V + s] = __floats2half2_rn((float)(u.r * iu), (float)(u.i * iu));
     }
-    for (int e = 0; e < 72; ++e) Aq[(size_t)e * V + s] = __float2half_rn((float)(A[(size_t)e * V + s] * ia));
+    for (int e = 0; e < 2 * CLOVER_PAIRS; ++e) {
+      cx<double> a = A[(size_t)e * V + s];
+      Aq[(size_t)e * V + s] = __floats2half2_rn((float)(a.r * ia), (float)(a.i * ia));
+    }
   } else {
     for (int e = 0; e < 36; ++e) stc_store(Uq, (size_t)e * V + s, U[(size_t)e * V + s]);
-    for (int e = 0; e < 72; ++e) Aq[(size_t)e * V + s] = (S)A[(size_t)e * V + s];
+    for (int e = 0; e < 2 * CLOVER_PAIRS; ++e) stc_store(Aq, (size_t)e * V + s, A[(size_t)e * V + s]);
   }
 }
 
@@ -208,7 +210,7 @@ __global__ void spinor_to_canonical_kernel(cx<double>* canon, const cx<T>* in, G
   canon[(r * V + lex_site(g, c)) * 12 + comp] = cvt<double>(in[idx]);
 }
 
-__global__ void clover_export_kernel(cx<double>* out, const double* A, Geom g) {
+__global__ void clover_export_kernel(cx<double>* out, const cx<double>* A, Geom g) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const size_t V = g.V;
@@ -216,13 +218,16 @@ __global__ void clover_export_kernel(cx<double>* out, const double* A, Geom g) {
   site_coords(g, s, c);
   const size_t lex = lex_site(g, c);
   for (int h = 0; h < 2; ++h) {
-    const double* Ah = A + (size_t)h * 36 * V;
+    const cx<double>* Ah = A + (size_t)h * CLOVER_PAIRS * V;
     cx<double>* o = out + (lex * 2 + h) * 36;
-    for (int k = 0; k < 6; ++k) o[k * 6 + k] = mk(Ah[(size_t)k * V + s], 0.0);
+    for (int k = 0; k < 3; ++k) {
+      const cx<double> d = Ah[(size_t)k * V + s];
+      o[(2 * k) * 6 + 2 * k] = mk(d.r, 0.0);
+      o[(2 * k + 1) * 6 + 2 * k + 1] = mk(d.i, 0.0);
+    }
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
-        int p = upper_index(i, j);
-        cx<double> v = mk(Ah[(size_t)(6 + 2 * p) * V + s], Ah[(size_t)(7 + 2 * p) * V + s]);
+        const cx<double> v = Ah[(size_t)(3 + upper_index(i, j)) * V + s];
         o[i * 6 + j] = v;
         o[j * 6 + i] = conj(v);
       }
@@ -235,21 +240,21 @@ void launch_gauge_import(cx<double>* U, const cx<double>* canon, const Geom& g, 
   gauge_import_kernel<<<nblk(g.V), TPB, 0, st>>>(U, canon, g);
 }
 
-void launch_clover_build(double* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st) {
+void launch_clover_build(cx<double>* A, const cx<double>* U, const Geom& g, double m0, double csw, hipStream_t st) {
   clover_kernel<<<nblk(g.V, 128), 128, 0, st>>>(A, U, g, m0, csw);
 }
 
 template <typename S>
-void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, S* Aq, float* Asc, const cx<double>* U, const double* A,
-                           const Geom& g, hipStream_t st) {
+void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, stc_t<S>* Aq, float* Asc, const cx<double>* U,
+                           const cx<double>* A, const Geom& g, hipStream_t st) {
   quantize_gauge_kernel<S><<<nblk(g.V), TPB, 0, st>>>(Uq, Usc, Aq, Asc, U, A, g.V);
 }
-template void launch_quantize_gauge<double>(stc_t<double>*, float*, double*, float*, const cx<double>*,
-                                            const double*, const Geom&, hipStream_t);
-template void launch_quantize_gauge<float>(stc_t<float>*, float*, float*, float*, const cx<double>*, const double*,
-                                           const Geom&, hipStream_t);
-template void launch_quantize_gauge<__half>(stc_t<__half>*, float*, __half*, float*, const cx<double>*,
-                                            const double*, const Geom&, hipStream_t);
+template void launch_quantize_gauge<double>(stc_t<double>*, float*, stc_t<double>*, float*, const cx<double>*,
+                                            const cx<double>*, const Geom&, hipStream_t);
+template void launch_quantize_gauge<float>(stc_t<float>*, float*, stc_t<float>*, float*, const cx<double>*,
+                                           const cx<double>*, const Geom&, hipStream_t);
+template void launch_quantize_gauge<__half>(stc_t<__half>*, float*, stc_t<__half>*, float*, const cx<double>*,
+                                            const cx<double>*, const Geom&, hipStream_t);
 
 template <typename T>
 void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
@@ -266,7 +271,7 @@ template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, co
 template void launch_spinor_to_canonical<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
 template void launch_spinor_to_canonical<float>(cx<double>*, const cx<float>*, const Geom&, int, hipStream_t);
 
-void launch_clover_export(cx<double>* out, const double* A, const Geom& g, hipStream_t st) {
+void launch_clover_export(cx<double>* out, const cx<double>* A, const Geom& g, hipStream_t st) {
   clover_export_kernel<<<nblk(g.V), TPB, 0, st>>>(out, A, g);
 }
 

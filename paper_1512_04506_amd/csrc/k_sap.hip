@@ -27,144 +27,207 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
-// in-block hops of direction MU using rho of the neighbouring sites from LDS
-template <int MU, typename T, typename S>
-__device__ inline void block_hops(cx<T> acc[4][3], const cx<T>* lds, int vb, const SitePos& p, const Geom& g,
+// in-block hops of direction MU for NR residual vectors from LDS
+template <int MU, int NR, typename T, typename S>
+__device__ inline void block_hops(cx<T> acc[NR][4][3], const cx<T>* lds, int vb, const SitePos& p, const Geom& g,
                                   const GaugeView<S>& gv, size_t V) {
-  cx<T> q[4][3];
+  cx<T> q[NR][4][3];
   if (p.lc[MU] < g.bs[MU] - 1) {
     const int ln = p.l + g.lstr[MU];
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) q[sp][k] = lds[(3 * sp + k) * vb + ln];
-    hop_spinor<MU, true, T, S>(acc, q, gv, p.S, V);
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[r][sp][k] = lds[(r * 12 + 3 * sp + k) * vb + ln];
+    hop_spinor_multi<MU, true, NR, T, S>(acc, q, gv, p.S, V);
   }
   if (p.lc[MU] > 0) {
     const int ln = p.l - g.lstr[MU];
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) q[sp][k] = lds[(3 * sp + k) * vb + ln];
-    hop_spinor<MU, false, T, S>(acc, q, gv, p.S - g.lstr[MU], V);
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[r][sp][k] = lds[(r * 12 + 3 * sp + k) * vb + ln];
+    hop_spinor_multi<MU, false, NR, T, S>(acc, q, gv, p.S - g.lstr[MU], V);
   }
 }
 
-template <typename T, typename S>
+// hops of the full operator for NR vectors read from global memory
+template <int MU, int NR, typename T, typename S>
+__device__ inline void full_hops(cx<T> acc[NR][4][3], const cx<T>* x, size_t rs, int nr, const SitePos& p,
+                                 const Geom& g, const GaugeView<S>& gv, size_t V) {
+  // the run-time predicate (always true) keeps the compiler from hoisting
+  // the loads of both hops above either of them
+  const bool live = g.V > 0;
+  cx<T> q[NR][4][3];
+  if (live) {
+    const int sn = nbr_fwd(g, p, MU);
+    const bool wrap = MU == 3 && p.lc[3] == g.bs[3] - 1 && p.bc[3] == g.NB[3] - 1;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) load_spinor<T, T, false>(q[r], x + (size_t)min(r, nr - 1) * rs, sn, V, -1, wrap ? (T)-1 : (T)1);
+    hop_spinor_multi<MU, true, NR, T, S>(acc, q, gv, p.S, V);
+  }
+  asm volatile("" ::: "memory");
+  if (live) {
+    const int sb = nbr_bwd(g, p, MU);
+    const bool wrap = MU == 3 && p.lc[3] == 0 && p.bc[3] == 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) load_spinor<T, T, false>(q[r], x + (size_t)min(r, nr - 1) * rs, sb, V, -1, wrap ? (T)-1 : (T)1);
+    hop_spinor_multi<MU, false, NR, T, S>(acc, q, gv, sb, V);
+  }
+}
+
+template <typename T, typename S, int NR>
 __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, const cx<T>* __restrict__ y,
-                                                        GaugeView<S> gv, Geom g, int colour, int n_mr, size_t rs) {
+                                                        GaugeView<S> gv, Geom g, int colour, int n_mr, size_t rs,
+                                                        int nrhs) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   const int vb = g.vblock;
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);          // [12][vb]
-  T* red = reinterpret_cast<T*>(lds + 12 * vb);               // [nwaves][3]
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);          // [NR][12][vb]
+  T* red = reinterpret_cast<T*>(lds + NR * 12 * vb);          // [nwaves][3 NR]
   const int nwaves = (blockDim.x + 63) / 64;
   // blocks of one colour are contiguous; the swizzle gives each XCD one
   // contiguous run of them (a compact lattice region and its halo)
   const int ci = colour * g.neven + xcd_swizzle(blockIdx.x, gridDim.x);
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - r0);  // rhs handled by this workgroup
   const int l = threadIdx.x;
   const bool act = l < vb;
   const size_t V = g.V;
-  x += (size_t)r * rs;
-  y += (size_t)r * rs;
+  x += (size_t)r0 * rs;
+  y += (size_t)r0 * rs;
 
   const int s = ci * vb + (act ? l : 0);
   const SitePos pos = site_pos(g, s);
-  cx<T> rho[4][3], e[4][3];
+  cx<T> rho[NR][4][3], e[NR][4][3];
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      rho[sp][k] = mk((T)0, (T)0);
-      e[sp][k] = mk((T)0, (T)0);
-    }
-  if (act) {
-    // residual r = y - D x with the current x (global memory)
-    cx<T> acc[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) acc[sp][k] = mk((T)0, (T)0);
-    cx<T> p[4][3];
-    load_spinor<T, T, false>(p, x, s, V, -1, (T)1);
-    clover_apply<T, S>(acc, p, gv, s, V);
-    hops_all<T, T, S, DS_FULL>(acc, x, gv, g, pos, 0, -1);
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) rho[sp][k] = y[(size_t)(3 * sp + k) * V + s] - acc[sp][k];
-  }
-
-  for (int it = 0; it < n_mr; ++it) {
-    // Launder the link/clover pointers: the loads of B below are the same in
-    // every MR step, and hoisting them out of the loop would pin ~200 values
-    // in registers for the whole kernel.
-    GaugeView<S> gvi = gv;
-    asm volatile("" : "+s"(gvi.U), "+s"(gvi.A));
-    if (act) {
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) lds[(3 * sp + k) * vb + l] = rho[sp][k];
-    }
-    __syncthreads();
-    cx<T> q[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) q[sp][k] = mk((T)0, (T)0);
-    T qr_re = 0, qr_im = 0, qq = 0;
-    if (act) {
-      clover_apply<T, S>(q, rho, gvi, s, V);
-      block_hops<0, T, S>(q, lds, vb, pos, g, gvi, V);
-      block_hops<1, T, S>(q, lds, vb, pos, g, gvi, V);
-      block_hops<2, T, S>(q, lds, vb, pos, g, gvi, V);
-      block_hops<3, T, S>(q, lds, vb, pos, g, gvi, V);
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          cx<T> t = cmulc(q[sp][k], rho[sp][k]);
-          qr_re += t.r;
-          qr_im += t.i;
-          qq += q[sp][k].r * q[sp][k].r + q[sp][k].i * q[sp][k].i;
-        }
-    }
-    qr_re = wave_sum(qr_re);
-    qr_im = wave_sum(qr_im);
-    qq = wave_sum(qq);
-    const int w = l >> 6;
-    if ((l & 63) == 0) {
-      red[3 * w + 0] = qr_re;
-      red[3 * w + 1] = qr_im;
-      red[3 * w + 2] = qq;
-    }
-    __syncthreads();
-    T a_re = 0, a_im = 0, n2 = 0;
-    for (int k = 0; k < nwaves; ++k) {
-      a_re += red[3 * k + 0];
-      a_im += red[3 * k + 1];
-      n2 += red[3 * k + 2];
-    }
-    cx<T> alpha = n2 > (T)0 ? mk(a_re / n2, a_im / n2) : mk((T)0, (T)0);
-    if (act) {
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          e[sp][k] = e[sp][k] + alpha * rho[sp][k];
-          rho[sp][k] = rho[sp][k] - alpha * q[sp][k];
-        }
-    }
-  }
-  if (act) {
+  for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        size_t i = (size_t)(3 * sp + k) * V + s;
-        x[i] = x[i] + e[sp][k];
+        rho[r][sp][k] = mk((T)0, (T)0);
+        e[r][sp][k] = mk((T)0, (T)0);
       }
+  if (act) {
+    // residual r = y - D x with the current x (global memory); a missing
+    // second rhs repeats the first and is never stored
+    cx<T> acc[NR][4][3], p[NR][4][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[r][sp][k] = mk((T)0, (T)0);
+      load_spinor<T, T, false>(p[r], x + (size_t)min(r, nr - 1) * rs, s, V, -1, (T)1);
+    }
+    clover_apply_multi<NR, T, S>(acc, p, gv, s, V);
+    full_hops<0, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    asm volatile("" ::: "memory");
+    full_hops<1, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    asm volatile("" ::: "memory");
+    full_hops<2, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    asm volatile("" ::: "memory");
+    full_hops<3, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          rho[r][sp][k] = y[(size_t)min(r, nr - 1) * rs + (size_t)(3 * sp + k) * V + s] - acc[r][sp][k];
+  }
+
+  for (int it = 0; it < n_mr; ++it) {
+    // Launder an offset of the link/clover pointers: the loads of B below are
+    // the same in every MR step, and hoisting them out of the loop would pin
+    // them in registers for the whole kernel.  (Laundering the pointers
+    // themselves would turn the loads into flat loads.)
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    GaugeView<S> gvi = gv;
+    gvi.U += zero;
+    gvi.A += zero;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) lds[(r * 12 + 3 * sp + k) * vb + l] = rho[r][sp][k];
+    }
+    __syncthreads();
+    cx<T> q[NR][4][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[r][sp][k] = mk((T)0, (T)0);
+    T dots[NR][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dots[r][0] = dots[r][1] = dots[r][2] = (T)0;
+    if (act) {
+      clover_apply_multi<NR, T, S>(q, rho, gvi, s, V);
+      block_hops<0, NR, T, S>(q, lds, vb, pos, g, gvi, V);
+      block_hops<1, NR, T, S>(q, lds, vb, pos, g, gvi, V);
+      block_hops<2, NR, T, S>(q, lds, vb, pos, g, gvi, V);
+      block_hops<3, NR, T, S>(q, lds, vb, pos, g, gvi, V);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const cx<T> t = cmulc(q[r][sp][k], rho[r][sp][k]);
+            dots[r][0] += t.r;
+            dots[r][1] += t.i;
+            dots[r][2] += q[r][sp][k].r * q[r][sp][k].r + q[r][sp][k].i * q[r][sp][k].i;
+          }
+    }
+    const int w = l >> 6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T v = wave_sum(dots[r][c]);
+        if ((l & 63) == 0) red[w * 3 * NR + 3 * r + c] = v;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T a_re = 0, a_im = 0, n2 = 0;
+      for (int k = 0; k < nwaves; ++k) {
+        a_re += red[k * 3 * NR + 3 * r + 0];
+        a_im += red[k * 3 * NR + 3 * r + 1];
+        n2 += red[k * 3 * NR + 3 * r + 2];
+      }
+      const cx<T> alpha = n2 > (T)0 ? mk(a_re / n2, a_im / n2) : mk((T)0, (T)0);
+      if (act) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            e[r][sp][k] = e[r][sp][k] + alpha * rho[r][sp][k];
+            rho[r][sp][k] = rho[r][sp][k] - alpha * q[r][sp][k];
+          }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nr) break;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const size_t i = (size_t)r * rs + (size_t)(3 * sp + k) * V + s;
+          x[i] = x[i] + e[r][sp][k];
+        }
+    }
   }
 }
 
@@ -174,11 +237,15 @@ template <typename T, typename S>
 void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, int colour, int n_mr, int nrhs,
                       hipStream_t st) {
   if (nrhs <= 0) return;
-  int threads = ((g.vblock + 63) / 64) * 64;
-  int nwaves = threads / 64;
-  size_t lds = (size_t)12 * g.vblock * sizeof(cx<T>) + (size_t)3 * nwaves * sizeof(T);
-  dim3 grid(g.nblocks / 2, nrhs);
-  sap_phase_kernel<T, S><<<grid, threads, lds, st>>>(x, y, gv, g, colour, n_mr, (size_t)12 * g.V);
+  const int threads = ((g.vblock + 63) / 64) * 64;
+  const int nwaves = threads / 64;
+  const size_t rs = (size_t)12 * g.V;
+  // two right-hand sides per thread share every link and clover load
+  // (FP32 arithmetic; the FP64 variant keeps one to fit the register file)
+  constexpr int NR = sizeof(T) == 4 ? 2 : 1;
+  const size_t lds = (size_t)NR * 12 * g.vblock * sizeof(cx<T>) + (size_t)3 * NR * nwaves * sizeof(T);
+  dim3 grid(g.nblocks / 2, (nrhs + NR - 1) / NR);
+  sap_phase_kernel<T, S, NR><<<grid, threads, lds, st>>>(x, y, gv, g, colour, n_mr, rs, nrhs);
 }
 
 template void launch_sap_phase<double, double>(cx<double>*, const cx<double>*, const GaugeView<double>&, const Geom&,

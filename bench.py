@@ -12,6 +12,7 @@ relative residual 1e-10, all inputs resident in HBM before the timed region.
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -30,6 +31,10 @@ WORKLOADS = {
     "c1": dict(L=(4, 4, 4, 4), block=(2, 2, 2, 2), eps=0.3, m0=-0.1, ntv=8, nrhs=1, rhs="gauss",
                seeds=(101, 102), name="4^4 eps0.3 m0-0.1 csw1 blocks2^4 Ntv8 1 gaussian rhs"),
 }
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counter runs calibrated on a stream kernel of known size; the
+# record names the sources it was taken from and is ignored once they change
+TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic_32x32x32x64.txt")
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32
 FP64_PEAK_TFLOPS = 78.6
@@ -121,6 +126,13 @@ def kernel_rooflines(dd, torch, ctx, w, reps=50):
     ms = time_kernel(torch, lambda: ctx.dirac_apply_internal(b64, a64, 1, dd.FP64), reps)
     bytes_site = 192 + 192 + 576 + 576
     out["dslash_fp64"] = dict(ms=ms, bytes=bytes_site * V, gbs=bytes_site * V / ms / 1e6)
+    # stream kernel dst = 1 * src over 2 GiB: the HBM rate this machine reaches,
+    # and the known-size reference for the traffic counters
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = time_kernel(torch, lambda: torch.mul(src, 1.0, out=dst), 10)
+    out["stream_2GiB"] = dict(ms=ms, bytes=2 << 31, gbs=(2 << 31) / ms / 1e6)
+    del src, dst
     # coarse stencil (FP16 D_c + per-(site, slot) scale, FP32 vectors)
     for nr in (1, w["nrhs"]):
         x = torch.randn(nr * nb * nc * 2, dtype=torch.float32, device="cuda")
@@ -180,6 +192,31 @@ def dominant_roofline(w, kt, prec):
            "avg_launch_ms": r["ms"] / r["launches"], "launches": r["launches"],
            "algorithmic_per_launch": r["per_launch"]}
     return out
+
+
+def sources_digest(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1512_04506_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind, workload):
+    """HBM bytes per launch of kernel class `kind` on `workload`, or None if
+    no counter record exists for the sources as they are now."""
+    try:
+        with open(TRAFFIC_RECORDS) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        if not line.startswith("record: "):
+            continue
+        r = json.loads(line[len("record: "):])
+        if r["class"] == kind and r["workload"] == workload and r["sources_sha256"] == sources_digest(r["sources"]):
+            return r["bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(w):
@@ -286,6 +323,7 @@ def main():
         "kernels_isolated": roof,
         "roofline": dominant_roofline(w, mixed["kernel_times"], dd.MIXED16),
     }
+    line["roofline"]["traffic"] = measured_traffic(line["roofline"]["kernel"], w["name"])
     if fp64:
         f64ms = sum(fp64["step_ms"]) / len(fp64["step_ms"])
         line["fp64"] = {"ms_per_step": f64ms, "setup_ms": sum(fp64["setup_ms"]) / len(fp64["setup_ms"]),

@@ -88,10 +88,15 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);          // [NR][12][vb]
   T* red = reinterpret_cast<T*>(lds + NR * 12 * vb);          // [nwaves][3 NR]
   const int nwaves = (blockDim.x + 63) / 64;
-  // blocks of one colour are contiguous; the swizzle gives each XCD one
-  // contiguous run of them (a compact lattice region and its halo)
-  const int ci = colour * g.neven + xcd_swizzle(blockIdx.x, gridDim.x);
-  const int r0 = blockIdx.y * NR;
+  // Workgroup = (block of the colour, group of NR rhs), rhs group fastest so
+  // that the workgroups sharing a block's links and clover run side by side.
+  // Blocks of one colour are contiguous; the swizzle gives each XCD one
+  // contiguous run of them (a compact lattice region and its halo, and the
+  // links read by all rhs groups of those blocks stay in that XCD's L2).
+  const int ngroup = (nrhs + NR - 1) / NR;
+  const int wl = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int ci = colour * g.neven + wl / ngroup;
+  const int r0 = (wl % ngroup) * NR;
   const int nr = min(NR, nrhs - r0);  // rhs handled by this workgroup
   const int l = threadIdx.x;
   const bool act = l < vb;
@@ -233,19 +238,31 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
 
 }  // namespace
 
+template <typename T, typename S, int NR>
+static void launch_sap_nr(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, int colour, int n_mr,
+                          int nrhs, hipStream_t st) {
+  const int threads = ((g.vblock + 63) / 64) * 64;
+  const int nwaves = threads / 64;
+  const size_t rs = (size_t)12 * g.V;
+  const size_t lds = (size_t)NR * 12 * g.vblock * sizeof(cx<T>) + (size_t)3 * NR * nwaves * sizeof(T);
+  const int grid = g.nblocks / 2 * ((nrhs + NR - 1) / NR);
+  sap_phase_kernel<T, S, NR><<<grid, threads, lds, st>>>(x, y, gv, g, colour, n_mr, rs, nrhs);
+}
+
 template <typename T, typename S>
 void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Geom& g, int colour, int n_mr, int nrhs,
                       hipStream_t st) {
   if (nrhs <= 0) return;
-  const int threads = ((g.vblock + 63) / 64) * 64;
-  const int nwaves = threads / 64;
-  const size_t rs = (size_t)12 * g.V;
-  // two right-hand sides per thread share every link and clover load
-  // (FP32 arithmetic; the FP64 variant keeps one to fit the register file)
-  constexpr int NR = sizeof(T) == 4 ? 2 : 1;
-  const size_t lds = (size_t)NR * 12 * g.vblock * sizeof(cx<T>) + (size_t)3 * NR * nwaves * sizeof(T);
-  dim3 grid(g.nblocks / 2, (nrhs + NR - 1) / NR);
-  sap_phase_kernel<T, S, NR><<<grid, threads, lds, st>>>(x, y, gv, g, colour, n_mr, rs, nrhs);
+  // FP32 arithmetic: two right-hand sides per thread share every link and
+  // clover load (a single rhs takes the one-vector kernel); FP64 keeps one
+  // per thread to fit the register file
+  if constexpr (sizeof(T) == 4) {
+    if (nrhs > 1) {
+      launch_sap_nr<T, S, 2>(x, y, gv, g, colour, n_mr, nrhs, st);
+      return;
+    }
+  }
+  launch_sap_nr<T, S, 1>(x, y, gv, g, colour, n_mr, nrhs, st);
 }
 
 template void launch_sap_phase<double, double>(cx<double>*, const cx<double>*, const GaugeView<double>&, const Geom&,

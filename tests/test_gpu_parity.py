@@ -153,6 +153,10 @@ def test_vcycle_deterministic(case, prec):
     ref = np.stack([M.vcycle(y[r]) for r in range(3)])
     tol = {0: 1e-10, 1: 1e-5, 2: 2e-2}[prec]
     assert rel(host(x), ref) <= tol
+    # a lone right-hand side goes through the one-vector smoother kernel
+    x1 = torch.zeros_like(dev(y[2:3]))
+    ctx.mg_apply(x1, dev(y[2:3].copy()), 1)
+    assert rel(host(x1)[0], ref[2]) <= tol
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])

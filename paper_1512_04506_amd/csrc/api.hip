@@ -74,6 +74,7 @@ struct DevBuf {
     if (p) (void)hipFree(p);
     p = nullptr;
   }
+  void swap(DevBuf& o) { std::swap(p, o.p); }
 };
 
 std::string g_create_error;
@@ -228,7 +229,7 @@ namespace {
 
 // Krylov workspace of one GMRES instance (coarse or outer)
 struct Krylov {
-  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, kdone, h1, h2, n2, part;
+  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, kdone, h1, h2, n2, part, wscale;
   int m = 0, maxr = 0, ldh = 0;
   ArnoldiState st{};
   void alloc(int m_, int maxr_, size_t n_per_rhs) {
@@ -248,6 +249,7 @@ struct Krylov {
     h1.alloc<cx<double>>((size_t)maxr * ldh);
     h2.alloc<cx<double>>((size_t)maxr * ldh);
     n2.alloc<cx<double>>(maxr);
+    wscale.alloc<double>(maxr);
     part.alloc<cx<double>>((size_t)maxr * (m + 1) * blas_nchunks(n_per_rhs));
     st.H = H.get<cx<double>>();
     st.cs = cs.get<cx<double>>();
@@ -279,11 +281,11 @@ struct Solver final : SolverBase {
   // the test vectors for the Gram-Schmidt, dequantised basis, D_c
   // accumulation buffer and one chunk of D_ij P_j columns
   DevBuf ws_Wd, ws_Wt, ws_D, ws_Z;
-  static constexpr int GAL_CHUNK = 8;
+  static constexpr int GAL_CHUNK = 32;  // all test vectors of one chirality per pass
   void ensure_setup_ws() {
     if (ws_Wd.p) return;
     ws_Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
-    ws_Wt.alloc<cx<T>>((size_t)g.ntv * fsz());
+    if (is_half<S>()) ws_Wt.alloc<cx<T>>((size_t)g.ntv * fsz());  // else the stored basis is already cx<T>
     ws_D.alloc<cx<T>>((size_t)g.nblocks * 9 * g.nc * g.nc);
     ws_Z.alloc<cx<T>>((size_t)std::min(g.ntv, GAL_CHUNK) * fsz());
   }
@@ -486,8 +488,13 @@ struct Solver final : SolverBase {
     ensure_setup_ws();
     cx<T>* D = ws_D.get<cx<T>>();
     HIPCK(hipMemsetAsync(D, 0, sizeof(cx<T>) * g.nblocks * 9 * nn, st));
-    cx<T>* Wtp = ws_Wt.get<cx<T>>();
-    launch_dequantize_basis<T, S>(Wtp, bv(), g, st);
+    const cx<T>* Wtp;
+    if constexpr (is_half<S>()) {
+      launch_dequantize_basis<T, S>(ws_Wt.get<cx<T>>(), bv(), g, st);
+      Wtp = ws_Wt.get<cx<T>>();
+    } else {
+      Wtp = reinterpret_cast<const cx<T>*>(Wq.get<stc_t<S>>());
+    }
     const int CH = std::min(g.ntv, (int)GAL_CHUNK);
     cx<T>* Zp = ws_Z.get<cx<T>>();
     for (int hp = 0; hp < 2; ++hp)
@@ -611,43 +618,63 @@ struct Solver final : SolverBase {
   // than half of |w|^2 in the projection (norm ratio below 1/sqrt 2), the
   // criterion of Daniel, Gragg, Kaufman and Stewart.  Returns whether the
   // second pass ran (its coefficients are then in h2).
-  bool cgs_dgks(cx<double>* V, size_t vsj, int k, int nrhs) {
+  // Classical Gram-Schmidt done twice against the outer basis V_0..V_k:
+  // h1 = V^H w; w <- w - V h1 and h2 = V^H w in one fused pass; the norm of
+  // w'' = w - V h2 from |w|^2 - |h2|^2 (V orthonormal); w <- w'' / |w''| in
+  // one pass.  The Arnoldi column is h1 + h2 with subdiagonal |w''|.
+  void cgs2(cx<double>* V, size_t vsj, int k, int nrhs) {
     const size_t n = fsz();
     const int* act = ok.active.get<int>();
     cx<double>* w = V + (size_t)(k + 1) * vsj;
-    launch_mdot<double>(ok.h1.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 2, w, n, n, nrhs,
+    launch_mdot<double>(ok.h1.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 1, w, n, n, nrhs,
                         act, st);
-    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h1.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
-    launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), w, 0, n, 1, w, n, n, nrhs, act, st);
-    // decide on the host: |w|^2 before (h1[k+1]) and after (n2), active rhs
-    HIPCK(hipMemcpy2DAsync(c->h_cx, sizeof(cx<double>), ok.h1.get<cx<double>>() + (k + 1),
-                           sizeof(cx<double>) * ok.ldh, sizeof(cx<double>), nrhs, hipMemcpyDeviceToHost, st));
-    HIPCK(hipMemcpyAsync(c->h_cx + 64, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost,
-                         st));
-    HIPCK(hipMemcpyAsync(c->h_flags, act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-    c->sync();
-    bool again = false;
-    for (int r = 0; r < nrhs; ++r)
-      if (c->h_flags[r] && c->h_cx[64 + r].r < 0.5 * c->h_cx[r].r) again = true;
-    if (!again) return false;
-    launch_mdot<double>(ok.h2.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 1, w, n, n, nrhs,
-                        act, st);
-    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h2.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
-    launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), w, 0, n, 1, w, n, n, nrhs, act, st);
-    return true;
+    if (k + 1 <= GS_FUSED_MAXV) {
+      launch_gs_fused(ok.h2.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 1, w, n,
+                      ok.h1.get<cx<double>>(), n, nrhs, act, st);
+    } else {  // long cycles: the same step in two passes (the last vector is w itself: |w|^2)
+      launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h1.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
+      launch_mdot<double>(ok.h2.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 2, w, n, n,
+                          nrhs, act, st);
+    }
+    launch_gs_norm(ok.n2.get<cx<double>>(), ok.wscale.get<double>(), ok.h2.get<cx<double>>(), ok.ldh, k + 1, nrhs,
+                   act, st);
+    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h2.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st,
+                                 ok.wscale.get<double>());
   }
 
+  // The outer basis V (FP64) and the preconditioned vectors Z grow with the
+  // Krylov dimension actually reached: a 12-rhs FP64 vector of the 32^3x64
+  // lattice is 4.8 GB, so a full FGMRES(20) basis would take most of HBM
+  // although a cycle usually stops after a few iterations.
+  int outer_cap = 0;  // vectors held by oV; oZ holds outer_cap - 1
   void ensure_outer(int m, int nrhs) {
     if (m == outer_m && nrhs <= outer_r) return;
     outer_m = m;
     outer_r = nrhs;
     const size_t n = fsz();
-    oV.alloc<cx<double>>((size_t)(m + 1) * nrhs * n);
-    oZ.alloc<cx<T>>((size_t)m * nrhs * n);
+    outer_cap = std::min(m + 1, 2);  // doubled on demand by grow_outer
+    oV.alloc<cx<double>>((size_t)outer_cap * nrhs * n);
+    oZ.alloc<cx<T>>((size_t)(outer_cap - 1) * nrhs * n);
     ow.alloc<cx<double>>((size_t)nrhs * n);
     of.alloc<cx<double>>((size_t)nrhs * n);
     ou.alloc<cx<double>>((size_t)nrhs * n);
     ok.alloc(m, nrhs, n);
+  }
+
+  // room for basis vectors 0..kv-1 (and Z vectors 0..kv-2), contents kept
+  void grow_outer(int kv) {
+    if (kv <= outer_cap) return;
+    const int cap = std::min(outer_m + 1, std::max(kv, 2 * outer_cap));
+    const size_t vs = (size_t)outer_r * fsz();
+    DevBuf nV, nZ;
+    nV.alloc<cx<double>>((size_t)cap * vs);
+    nZ.alloc<cx<T>>((size_t)(cap - 1) * vs);
+    HIPCK(hipMemcpyAsync(nV.p, oV.p, sizeof(cx<double>) * outer_cap * vs, hipMemcpyDeviceToDevice, st));
+    HIPCK(hipMemcpyAsync(nZ.p, oZ.p, sizeof(cx<T>) * (outer_cap - 1) * vs, hipMemcpyDeviceToDevice, st));
+    c->sync();
+    oV.swap(nV);
+    oZ.swap(nZ);
+    outer_cap = cap;
   }
 
   int solve(double* u_canon, const double* f_canon, int nrhs, double tol) override {
@@ -714,6 +741,9 @@ struct Solver final : SolverBase {
       launch_scale<double, double>(V, n, V, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
       int k = 0;
       for (; k < m && its < c->p.outer_maxit; ++k) {
+        grow_outer(k + 2);
+        V = oV.get<cx<double>>();
+        Z = oZ.get<cx<T>>();
         cx<double>* vk = V + (size_t)k * vsj;
         cx<T>* zk = Z + (size_t)k * vsj;
         // z_k = M^{-1} v_k
@@ -727,10 +757,9 @@ struct Solver final : SolverBase {
           else
             launch_dslash<float, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
         });
-        const bool second = c->timed_ret(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { return cgs_dgks(V, vsj, k, nrhs); });
-        launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), second ? ok.h2.get<cx<double>>() : nullptr, ok.ldh,
+        c->timed(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { cgs2(V, vsj, k, nrhs); });
+        launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), ok.h2.get<cx<double>>(), ok.ldh,
                               ok.n2.get<cx<double>>(), 1, nrhs, st);
-        launch_scale<double, double>(wk, n, wk, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
         ++its;
         if (!read_any_active(ok, nrhs)) {
           ++k;

@@ -282,7 +282,17 @@ void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size
 // w[r] += sign * sum_j h[r * ldh + j] * V_j[r]
 template <typename Tw, typename Tv>
 void launch_maxpy(cx<Tw>* w, size_t wstride_r, const cx<Tv>* Vb, size_t vstride_j, size_t vstride_r, int nvec,
-                  const cx<double>* h, int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st);
+                  const cx<double>* h, int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st,
+                  const double* post = nullptr);
+// Fused second Gram-Schmidt pass over FP64 vectors: w <- w - V h1, then
+// h2[r][j] = V_j^H w (j < nvec) and h2[r][nvec] = |w|^2, nvec <= GS_FUSED_MAXV
+constexpr int GS_FUSED_MAXV = 24;
+void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>* Vb, size_t vstride_j,
+                     size_t vstride_r, int nvec, cx<double>* w, size_t wstride_r, const cx<double>* h1, size_t n,
+                     int nrhs, const int* active, hipStream_t st);
+// n2[r] = h2[r][nvec] - sum_{j<nvec} |h2[r][j]|^2, inv[r] = 1/sqrt(n2[r]) (0 if not positive)
+void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs,
+                    const int* active, hipStream_t st);
 // y[r] = s[r] * x[r] (s real double, per rhs) ; y and x may alias
 template <typename Ty, typename Tx>
 void launch_scale(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, const double* s, size_t n, int nrhs,

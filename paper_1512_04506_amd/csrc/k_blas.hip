@@ -75,20 +75,94 @@ __global__ void mdot_final_kernel(cx<double>* h, int ldh, const cx<double>* part
   if (threadIdx.x == 0) h[(size_t)r * ldh + j] = mk(re, im);
 }
 
+// w <- (w + sign sum_j h_j V_j) [* post[r] if post]
 template <typename Tw, typename Tv>
 __global__ __launch_bounds__(BT) void maxpy_kernel(cx<Tw>* w, size_t wsr, const cx<Tv>* __restrict__ Vb, size_t vsj,
                                                    size_t vsr, int nvec, const cx<double>* __restrict__ h, int ldh,
-                                                   double sign, size_t n, const int* active) {
+                                                   double sign, size_t n, const int* active, const double* post) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   using Tc = typename std::conditional<(sizeof(Tw) > sizeof(Tv)), Tw, Tv>::type;
   const cx<double>* hr = h + (size_t)r * ldh;
+  const Tc f = post ? (Tc)post[r] : (Tc)1;
   for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < n; i += (size_t)gridDim.x * BT) {
     cx<Tc> acc = cvt<Tc>(w[(size_t)r * wsr + i]);
     for (int j = 0; j < nvec; ++j)
       acc = acc + cvt<Tc>(sign * hr[j]) * cvt<Tc>(Vb[(size_t)j * vsj + (size_t)r * vsr + i]);
-    w[(size_t)r * wsr + i] = cvt<Tw>(acc);
+    w[(size_t)r * wsr + i] = cvt<Tw>(f * acc);
   }
+}
+
+// Second step of classical Gram-Schmidt done twice, in one pass over the
+// data: w <- w - sum_j h_j V_j, then the partial sums of V_j^H w (j < nvec)
+// and |w|^2 (entry nvec) of the updated w, as mdot_partial_kernel writes
+// them.  The nvec basis entries of an element stay in registers between
+// the update and the inner products, so every vector is read once.
+template <int MAXV>
+__global__ __launch_bounds__(BT) void gs_fused_kernel(cx<double>* part, const cx<double>* __restrict__ Vb, size_t vsj,
+                                                      size_t vsr, int nvec, cx<double>* w, size_t wsr,
+                                                      const cx<double>* __restrict__ h, int ldh, size_t n,
+                                                      size_t chunk, int nchunk, const int* active) {
+  __shared__ cx<double> red[MAXV + 1][BT / 64];
+  const int c = blockIdx.x;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const size_t beg = (size_t)c * chunk;
+  const size_t end = min(n, beg + chunk);
+  cx<double>* wr = w + (size_t)r * wsr;
+  const cx<double>* hr = h + (size_t)r * ldh;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  cx<double> acc[MAXV];
+  double nacc = 0.0;
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) acc[j] = mk(0.0, 0.0);
+  for (size_t i = beg + threadIdx.x; i < end; i += BT) {
+    cx<double> v[MAXV];
+    cx<double> x = wr[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nvec) {
+        v[j] = Vb[(size_t)j * vsj + (size_t)r * vsr + i];
+        x = x - hr[j] * v[j];
+      }
+    wr[i] = x;
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nvec) acc[j] = acc[j] + cmulc(v[j], x);
+    nacc += x.r * x.r + x.i * x.i;
+  }
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    if (j < nvec) {
+      const double re = wave_sum_d(acc[j].r), im = wave_sum_d(acc[j].i);
+      if (lane == 0) red[j][wid] = mk(re, im);
+    }
+  }
+  nacc = wave_sum_d(nacc);
+  if (lane == 0) red[nvec][wid] = mk(nacc, 0.0);
+  __syncthreads();
+  for (int j = threadIdx.x; j <= nvec; j += BT) {
+    cx<double> sum = mk(0.0, 0.0);
+    for (int k = 0; k < BT / 64; ++k) sum = sum + red[j][k];
+    part[((size_t)r * (nvec + 1) + j) * nchunk + c] = sum;
+  }
+}
+
+// |w''|^2 = |w'|^2 - sum_j |h2_j|^2 (w'' = w' - V h2 with V orthonormal),
+// and the factor that normalises w''; zero for a vanishing or non-finite
+// norm (the Arnoldi step then stops that rhs)
+__global__ void gs_norm_kernel(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs,
+                               const int* active) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  if (active && !active[r]) return;
+  const cx<double>* hr = h2 + (size_t)r * ldh;
+  double t = hr[nvec].r;
+  for (int j = 0; j < nvec; ++j) t -= hr[j].r * hr[j].r + hr[j].i * hr[j].i;
+  t = fmax(t, 0.0);
+  n2[r] = mk(t, 0.0);
+  const double nr = sqrt(t);
+  inv[r] = (nr > 0.0 && isfinite(nr)) ? 1.0 / nr : 0.0;
 }
 
 template <typename Ty, typename Tx>
@@ -278,9 +352,26 @@ void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size
 
 template <typename Tw, typename Tv>
 void launch_maxpy(cx<Tw>* w, size_t wsr, const cx<Tv>* Vb, size_t vsj, size_t vsr, int nvec, const cx<double>* h,
-                  int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st) {
-  if (nrhs <= 0 || nvec <= 0) return;
-  maxpy_kernel<Tw, Tv><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(w, wsr, Vb, vsj, vsr, nvec, h, ldh, sign, n, active);
+                  int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st, const double* post) {
+  if (nrhs <= 0 || (nvec <= 0 && !post)) return;
+  maxpy_kernel<Tw, Tv>
+      <<<dim3(grid_for(n), nrhs), BT, 0, st>>>(w, wsr, Vb, vsj, vsr, nvec, h, ldh, sign, n, active, post);
+}
+
+void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>* Vb, size_t vsj, size_t vsr,
+                     int nvec, cx<double>* w, size_t wsr, const cx<double>* h1, size_t n, int nrhs, const int* active,
+                     hipStream_t st) {
+  if (nrhs <= 0 || nvec <= 0 || nvec > GS_FUSED_MAXV) return;
+  const int nchunk = blas_nchunks(n);
+  const size_t chunk = (n + nchunk - 1) / nchunk;
+  gs_fused_kernel<GS_FUSED_MAXV><<<dim3(nchunk, nrhs), BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n,
+                                                                    chunk, nchunk, active);
+  mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
+}
+
+void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs, const int* active,
+                    hipStream_t st) {
+  gs_norm_kernel<<<1, 64, 0, st>>>(n2, inv, h2, ldh, nvec, nrhs, active);
 }
 
 template <typename Ty, typename Tx>
@@ -320,7 +411,7 @@ template void launch_mdot<float>(cx<double>*, int, cx<double>*, const cx<float>*
                                  const cx<float>*, size_t, size_t, int, const int*, hipStream_t);
 #define INST2(A, B)                                                                                                   \
   template void launch_maxpy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, const cx<double>*, int, double, \
-                                   size_t, int, const int*, hipStream_t);                                             \
+                                   size_t, int, const int*, hipStream_t, const double*);                              \
   template void launch_scale<A, B>(cx<A>*, size_t, const cx<B>*, size_t, const double*, size_t, int, const int*,      \
                                    hipStream_t);                                                                      \
   template void launch_copy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, hipStream_t);

@@ -29,8 +29,13 @@ using namespace dev;
 template <typename Tin, typename Tout, typename S, typename Tc, int MODE>
 __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out, const cx<Tin>* __restrict__ in,
                                                      GaugeView<S> gv, Geom g, int mu_sel, int chi_in, size_t in_rs,
-                                                     size_t out_rs) {
-  const int ls = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;  // lexicographic-block order
+                                                     size_t out_rs, int nrhs) {
+  // workgroup = (run of 256 sites, rhs) with the rhs fastest, so the
+  // workgroups that read the same links and clover run side by side on one
+  // XCD and share its L2
+  const int wl = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int r = wl % nrhs;
+  const int ls = (wl / nrhs) * blockDim.x + threadIdx.x;  // lexicographic-block order
   if (ls >= g.V) return;
   const int bl = ls / g.vblock;
   int bc[4];
@@ -39,7 +44,6 @@ __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out,
   bc[2] = (bl / (g.NB[0] * g.NB[1])) % g.NB[2];
   bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
   const int s = block_to_int(g, bc) * g.vblock + (ls - bl * g.vblock);
-  const int r = blockIdx.y;
   const cx<Tin>* ip = in + (size_t)r * in_rs;
   cx<Tout>* op = out + (size_t)r * out_rs;
   const size_t V = g.V;
@@ -67,21 +71,21 @@ template <typename Tin, typename Tout, typename S, typename Tc>
 void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mode,
                    int mu, int chi_in, size_t in_rstride, size_t out_rstride, hipStream_t st) {
   if (nrhs <= 0) return;
-  dim3 grid((g.V + TPB - 1) / TPB, nrhs);
+  const unsigned grid = (unsigned)((g.V + TPB - 1) / TPB) * (unsigned)nrhs;
   switch (mode) {
     case DS_FULL:
-      dslash_kernel<Tin, Tout, S, Tc, DS_FULL><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride);
+      dslash_kernel<Tin, Tout, S, Tc, DS_FULL><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride, nrhs);
       break;
     case DS_BLOCK:
-      dslash_kernel<Tin, Tout, S, Tc, DS_BLOCK><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride);
+      dslash_kernel<Tin, Tout, S, Tc, DS_BLOCK><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride, nrhs);
       break;
     case DS_CROSS_FWD:
       dslash_kernel<Tin, Tout, S, Tc, DS_CROSS_FWD><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride,
-                                                                          out_rstride);
+                                                                          out_rstride, nrhs);
       break;
     default:
       dslash_kernel<Tin, Tout, S, Tc, DS_CROSS_BWD><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride,
-                                                                          out_rstride);
+                                                                          out_rstride, nrhs);
       break;
   }
 }

@@ -182,32 +182,41 @@ __global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, stc_t<S>* Aq, fl
 }
 
 // internal element (r, comp, S) <-> canonical element (r, lex(S), comp)
+// One thread per (rhs, internal site): the 12 components of a canonical site
+// are one contiguous 192-byte record, the internal components are 12
+// site-contiguous planes, so both sides are read/written in full lines.
 template <typename T>
 __global__ void spinor_to_internal_kernel(cx<T>* out, const cx<double>* canon, Geom g, int nrhs) {
   const size_t V = g.V;
-  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)nrhs * 12 * V) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nrhs * V) return;
   const int s = (int)(idx % V);
-  const size_t rc = idx / V;
-  const int comp = (int)(rc % 12);
-  const size_t r = rc / 12;
+  const size_t r = idx / V;
   int c[4];
   site_coords(g, s, c);
-  out[idx] = cvt<T>(canon[(r * V + lex_site(g, c)) * 12 + comp]);
+  const cx<double>* src = canon + (r * V + lex_site(g, c)) * 12;
+  cx<double> v[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = src[k];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[(r * 12 + k) * V + s] = cvt<T>(v[k]);
 }
 
 template <typename T>
 __global__ void spinor_to_canonical_kernel(cx<double>* canon, const cx<T>* in, Geom g, int nrhs) {
   const size_t V = g.V;
-  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)nrhs * 12 * V) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nrhs * V) return;
   const int s = (int)(idx % V);
-  const size_t rc = idx / V;
-  const int comp = (int)(rc % 12);
-  const size_t r = rc / 12;
+  const size_t r = idx / V;
   int c[4];
   site_coords(g, s, c);
-  canon[(r * V + lex_site(g, c)) * 12 + comp] = cvt<double>(in[idx]);
+  cx<double> v[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = cvt<double>(in[(r * 12 + k) * V + s]);
+  cx<double>* dst = canon + (r * V + lex_site(g, c)) * 12;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) dst[k] = v[k];
 }
 
 __global__ void clover_export_kernel(cx<double>* out, const cx<double>* A, Geom g) {
@@ -259,12 +268,12 @@ template void launch_quantize_gauge<__half>(stc_t<__half>*, float*, stc_t<__half
 template <typename T>
 void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * 12 * g.V;
-  if (n) spinor_to_internal_kernel<T><<<nblk(n), TPB, 0, st>>>(out, canon, g, nrhs);
+  if (n) spinor_to_internal_kernel<T><<<nblk(n / 12), TPB, 0, st>>>(out, canon, g, nrhs);
 }
 template <typename T>
 void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * 12 * g.V;
-  if (n) spinor_to_canonical_kernel<T><<<nblk(n), TPB, 0, st>>>(canon, in, g, nrhs);
+  if (n) spinor_to_canonical_kernel<T><<<nblk(n / 12), TPB, 0, st>>>(canon, in, g, nrhs);
 }
 template void launch_spinor_to_internal<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
 template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, const Geom&, int, hipStream_t);

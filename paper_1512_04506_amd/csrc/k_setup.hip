@@ -17,99 +17,109 @@ namespace {
 
 constexpr int QR_THREADS = 256;
 constexpr int MAX_NTV = 32;
-constexpr int TI = 2;                       // Gram tile: TI test vectors (rows of G)
-constexpr int TJ = 4;                       //            x TJ test vectors (columns)
-constexpr int GNV = TI * TJ * 2;            // real partial sums per lane and tile
+constexpr int QR_U = 4;  // 4-row slices per load round of the Gram matrix
+// One workgroup per aggregate (internal block ci, chirality h): rows are the
+// 6 V_block (spin of chirality h x colour, site) entries, columns the ntv
+// test vectors.  Per CholQR pass:
+//   G = X^H X: on the FP64 matrix cores.  A 16x16x4 f64 MFMA takes, in lane
+//              l, entry (row l/16, column l%16) of a 4-row slice for both of
+//              its operands, so one load per lane and column tile feeds all
+//              of Re/Im X^T X; the waves split the rows and their partial
+//              tiles are summed through LDS.  Every entry of X is read once.
+//   G = T^H T: Cholesky (real positive diagonal) across the workgroup and
+//              T^{-1} by back substitution;
+//   X <- X T^{-1}: each lane updates the rows of its own site (coalesced,
+//              in place).
+typedef double qr_v4d __attribute__((ext_vector_type(4)));
 
-template <int HALF, typename T>
-__device__ inline void rs_step(T v[GNV], int lane) {
-  const bool up = (lane & HALF) != 0;
-#pragma unroll
-  for (int j = 0; j < HALF; ++j) {
-    const T send = up ? v[j] : v[j + HALF];
-    const T keep = up ? v[j + HALF] : v[j];
-    v[j] = keep + __shfl_xor(send, HALF, 64);
-  }
-  if constexpr (HALF > 1) rs_step<HALF / 2, T>(v, lane);
-}
-
-// lane i (i < GNV) ends with the sum over the 64 lanes of v[i]
-template <typename T>
-__device__ inline T reduce_scatter(T v[GNV], int lane) {
-#pragma unroll
-  for (int o = 32; o >= GNV; o >>= 1)
-#pragma unroll
-    for (int j = 0; j < GNV; ++j) v[j] += __shfl_xor(v[j], o, 64);
-  rs_step<GNV / 2, T>(v, lane);
-  return v[0];
-}
-
-// One workgroup per aggregate (internal block ci, chirality h); one lane per
-// site of the block, which owns the aggregate's 6 rows of that site (spins
-// of chirality h x colours).  Per CholQR pass:
-//   G = X^H X: tiles of TI x TJ entries, each lane summing its 6 rows, the
-//              64 lanes by a shuffle butterfly and the waves through LDS;
-//   G = T^H T: Cholesky (real positive diagonal) and T^{-1} by one thread;
-//   X <- X T^{-1}: each lane updates its own rows (coalesced in-place).
 __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W, Geom g, int* status) {
   __shared__ cx<double> G[MAX_NTV][MAX_NTV];
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];  // T^{-1}, upper triangular
-  __shared__ double red[QR_THREADS / 64][MAX_NTV / TI][GNV];
+  __shared__ qr_v4d part[2][6][64];            // partial tiles of two waves
   __shared__ int fail;
   const int ci = blockIdx.x >> 1;  // internal block: its sites are ci * vblock + [0, vblock)
   const int h = blockIdx.x & 1;
   const int n = g.ntv;
   const size_t V = g.V;
+  const int vb = g.vblock;
   const int l = threadIdx.x, lane = l & 63, w = l >> 6;
-  const int nw = blockDim.x >> 6;
-  const bool act = l < g.vblock;
-  const size_t site = (size_t)ci * g.vblock + (act ? l : 0);
-  const double m = act ? 1.0 : 0.0;
+  const bool act = l < vb;
+  const size_t site = (size_t)ci * vb + (act ? l : 0);
+  const size_t base = (size_t)ci * vb;
   auto X = [&](int a, int k) -> cx<double>* { return W + ((size_t)a * 12 + 6 * h + k) * V + site; };
-  const int nti = (n + TI - 1) / TI, ntj = (n + TJ - 1) / TJ;
+  const bool two = n > 16;           // second column tile (columns 16..31)
+  const int nsteps = (6 * vb + 3) / 4;  // 4-row slices
+  const int col0 = lane & 15, rsub = lane >> 4;
+  const int a0 = min(col0, n - 1), a1 = min(16 + col0, n - 1);
+  const double m0 = col0 < n ? 1.0 : 0.0, m1 = 16 + col0 < n ? 1.0 : 0.0;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int jt = 0; jt < ntj; ++jt) {
-      cx<double> xj[6][TJ];
+    // tiles: 0 = Re(0,0) 1 = Im(0,0) 2 = Re(0,1) 3 = Im(0,1) 4 = Re(1,1) 5 = Im(1,1)
+    qr_v4d acc[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
+    for (int t = 0; t < 6; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
+    // QR_U slices per round: all loads of a round are issued before its
+    // MFMAs, so a wave has 2 QR_U loads in flight instead of 2
+    for (int s0 = w; s0 < nsteps; s0 += 4 * QR_U) {
+      cx<double> x0[QR_U], x1[QR_U];
 #pragma unroll
-        for (int q = 0; q < TJ; ++q) {
-          const int a = min(jt * TJ + q, n - 1);
-          const double mm = (jt * TJ + q < n) ? m : 0.0;
-          xj[k][q] = mm * *X(a, k);
-        }
-      for (int it = 0; it < nti; ++it) {
-        double v[GNV];
-#pragma unroll
-        for (int p = 0; p < TI; ++p) {
-          const int a = min(it * TI + p, n - 1);
-          const double mm = (it * TI + p < n) ? m : 0.0;
-          cx<double> xi[6];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) xi[k] = mm * *X(a, k);
-#pragma unroll
-          for (int q = 0; q < TJ; ++q) {
-            cx<double> acc = mk(0.0, 0.0);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) acc = cfmac(xi[k], xj[k][q], acc);
-            v[(p * TJ + q) * 2] = acc.r;
-            v[(p * TJ + q) * 2 + 1] = acc.i;
-          }
-        }
-        const double mine = reduce_scatter(v, lane);
-        if (lane < GNV) red[w][it][lane] = mine;
+      for (int u = 0; u < QR_U; ++u) {
+        const int row = 4 * (s0 + 4 * u) + rsub;
+        const bool live = row < 6 * vb;
+        const int c = live ? row / vb : 0, sr = live ? row % vb : 0;
+        const double mr = live ? 1.0 : 0.0;
+        const cx<double>* xp = W + (size_t)(6 * h + c) * V + base + sr;
+        x0[u] = (mr * m0) * xp[(size_t)a0 * 12 * V];
+        if (two) x1[u] = (mr * m1) * xp[(size_t)a1 * 12 * V];
       }
-      __syncthreads();
-      for (int e = l; e < nti * GNV; e += blockDim.x) {
-        const int it = e / GNV, idx = e % GNV;
-        double t = 0.0;
-        for (int k = 0; k < nw; ++k) t += red[k][it][idx];
-        const int part = idx & 1, pq = idx >> 1, p = pq / TJ, q = pq % TJ;
-        const int i = it * TI + p, j = jt * TJ + q;
-        if (i < n && j < n) reinterpret_cast<double*>(&G[i][j])[part] = t;
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const cx<double> y0 = x0[u];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
+        if (two) {
+          const cx<double> y1 = x1[u];
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.r, acc[2], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y1.i, acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.i, acc[3], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y1.r, acc[3], 0, 0, 0);
+          acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.r, acc[4], 0, 0, 0);
+          acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.i, y1.i, acc[4], 0, 0, 0);
+          acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.i, acc[5], 0, 0, 0);
+          acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1.i, y1.r, acc[5], 0, 0, 0);
+        }
       }
-      __syncthreads();
     }
+    // sum the four waves' tiles: waves 2,3 hand theirs to waves 0,1, then
+    // wave 1 to wave 0, which writes G (upper triangle and the (1,0) tile
+    // never read)
+    if (w >= 2)
+#pragma unroll
+      for (int t = 0; t < 6; ++t) part[w - 2][t][lane] = acc[t];
+    __syncthreads();
+    if (w < 2)
+#pragma unroll
+      for (int t = 0; t < 6; ++t) acc[t] += part[w][t][lane];
+    __syncthreads();
+    if (w == 1)
+#pragma unroll
+      for (int t = 0; t < 6; ++t) part[0][t][lane] = acc[t];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) acc[t] += part[0][t][lane];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = rsub + 4 * v, j = col0;  // f64 16x16x4 result: row l/16 + 4v, column l%16
+        if (i < n && j < n) G[i][j] = mk(acc[0][v], acc[1][v]);
+        if (two) {
+          if (i < n && 16 + j < n) G[i][16 + j] = mk(acc[2][v], acc[3][v]);
+          if (16 + i < n && 16 + j < n) G[16 + i][16 + j] = mk(acc[4][v], acc[5][v]);
+        }
+      }
+    }
+    __syncthreads();
     // Cholesky G = T^H T (T upper, real positive diagonal), right-looking,
     // in place in the upper triangle of G: step k scales row k by the pivot
     // and updates the trailing upper triangle, its entries spread over the

@@ -508,7 +508,8 @@ struct Solver final : SolverBase {
           cx<T>* out = D + (size_t)slot * nn + (size_t)(hp * g.ntv + a0) * nc;
           c->timed(DDAMG_KERNEL_SETUP_GALERKIN, na, [&] {
             launch_dslash<T, T, T, T>(Zp, in, gva, g, na, mode, mu, hp, fsz(), fsz(), st);
-            launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, na, st);
+            // a block-crossing piece lives on the last layer of the block only
+            launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, na, st, piece == 0 ? -1 : mu);
           });
         }
       }

@@ -159,6 +159,21 @@ __host__ __device__ inline int site_index(const Geom& g, const int c[4]) {
   for (int m = 3; m >= 0; --m) l = l * g.bs[m] + (c[m] - bc[m] * g.bs[m]);
   return block_to_int(g, bc) * g.vblock + l;
 }
+// in-block index of face site f (0 <= f < vblock / bs[mu]) of the layer
+// lc[mu] = layer, the other local coordinates lexicographic
+__host__ __device__ inline int face_site(const Geom& g, int mu, int layer, int f) {
+  int lc[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    if (d == mu) {
+      lc[d] = layer;
+    } else {
+      lc[d] = f % g.bs[d];
+      f /= g.bs[d];
+    }
+  }
+  return lc[0] + g.bs[0] * (lc[1] + g.bs[1] * (lc[2] + g.bs[2] * lc[3]));
+}
 // MI355X has 8 XCDs with separate L2 caches and hands out consecutive
 // workgroup ids round-robin over them.  xcd_swizzle maps the hardware id to
 // a logical id such that each XCD works on one contiguous 1/8 of the
@@ -223,6 +238,8 @@ void launch_clover_export(cx<double>* out, const cx<double>* A, const Geom& g, h
 
 // dslash: out[r] = piece of D applied to in[r] (chi_in >= 0 keeps only that
 // chirality of the input; mu selects the direction of the cross variants).
+// The cross variants write only the block layer they reach (lc[mu] = bs - 1
+// forward, 0 backward); out keeps its values on every other site.
 template <typename Tin, typename Tout, typename S, typename Tc>
 void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mode,
                    int mu, int chi_in, size_t in_rstride, size_t out_rstride, hipStream_t st);
@@ -234,10 +251,12 @@ void launch_sap_phase(cx<T>* x, const cx<T>* y, const GaugeView<S>& gv, const Ge
                       hipStream_t st);
 
 // restriction / prolongation; coarse output addressed as
-// out[r * ostr_r + cint(b) * ostr_b + h * ntv + a]
+// out[r * ostr_r + cint(b) * ostr_b + h * ntv + a].  face_mu >= 0: only the
+// last layer of every block in direction face_mu (lc[face_mu] =
+// bs[face_mu] - 1) is summed, whatever y holds elsewhere.
 template <typename T, typename S>
 void launch_restrict(cx<T>* out, size_t ostr_r, size_t ostr_b, const cx<T>* y, size_t ystr, const BasisView<S>& bv,
-                     const Geom& g, int nrhs, hipStream_t st);
+                     const Geom& g, int nrhs, hipStream_t st, int face_mu = -1);
 template <typename T, typename S>
 void launch_prolong(cx<T>* x, size_t xstr, const cx<T>* xc, size_t cstr, const BasisView<S>& bv, const Geom& g,
                     int nrhs, hipStream_t st);

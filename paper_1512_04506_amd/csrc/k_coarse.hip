@@ -70,7 +70,7 @@ __device__ inline T reduce_scatter(T v[NV], int lane) {
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void restrict_kernel(cx<T>* __restrict__ out, size_t ostr_r, size_t ostr_b,
                                                        const cx<T>* __restrict__ y, size_t ystr, BasisView<S> bv,
-                                                       Geom g, int nrhs) {
+                                                       Geom g, int nrhs, int face_mu) {
   constexpr int RT = RTile<T>::RT, AT = RTile<T>::AT, NV = RTile<T>::NV;
   constexpr int MAXAT = 32 / AT;  // ntv <= 32
   __shared__ T red[4][MAXAT][NV];
@@ -82,6 +82,12 @@ __global__ __launch_bounds__(256) void restrict_kernel(cx<T>* __restrict__ out, 
   const size_t V = g.V;
   const size_t site = (size_t)ci * g.vblock + (act ? l : 0);
   const int nat = (g.ntv + AT - 1) / AT;
+  bool onface = true;  // face_mu >= 0: only the last layer in direction face_mu holds data
+  if (face_mu >= 0) {
+    int lc[4];
+    local_coords(g, act ? l : 0, lc);
+    onface = lc[face_mu] == g.bs[face_mu] - 1;
+  }
   for (int r0 = 0; r0 < nrhs; r0 += RT) {
     const int nr = min(RT, nrhs - r0);
     // Every load below is unconditional (clamped to valid addresses and
@@ -90,10 +96,13 @@ __global__ __launch_bounds__(256) void restrict_kernel(cx<T>* __restrict__ out, 
     cx<T> yv[RT][12];
 #pragma unroll
     for (int j = 0; j < RT; ++j) {
-      const T m = (act && j < nr) ? (T)1 : (T)0;
+      const bool m = act && j < nr && onface;
       const size_t r = (size_t)min(r0 + j, nrhs - 1);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) yv[j][k] = m * y[r * ystr + (size_t)k * V + site];
+      for (int k = 0; k < 12; ++k) {
+        const cx<T> v = y[r * ystr + (size_t)k * V + site];
+        yv[j][k] = m ? v : mk((T)0, (T)0);  // a select: the other layers may hold stale values
+      }
     }
     // no barrier inside this loop: each wave parks its reduced values per
     // test-vector tile and runs ahead
@@ -137,6 +146,117 @@ __global__ __launch_bounds__(256) void restrict_kernel(cx<T>* __restrict__ out, 
       }
     }
     __syncthreads();
+  }
+}
+
+// Restriction on the FP32 matrix cores, for many right-hand sides: per
+// block and chirality h, C (ntv x 32 rhs) = W_h^H Y_h is a GEMM over the rows
+// (site, spin-colour of chirality h).  v_mfma_f32_32x32x2f32 takes A[i][k]
+// in lane i + 32 k and B[k][j] in lane j + 32 k and leaves C[i][j] in lane
+// j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.  The sites along k
+// cannot be spread over the lanes, so chunks of RM_CS sites are first read
+// with coalesced site-contiguous loads into LDS (basis scaled to FP32, rows
+// (site, component)), then fed to the MFMAs from there.  The complex
+// product takes four real GEMMs: conj(W) Y = (Wr Yr + Wi Yi) + i (Wr Yi -
+// Wi Yr).  Waves 2h and 2h+1 take the two halves of each chunk's rows of
+// chirality h and are summed through LDS at the end.
+typedef float mf_v16 __attribute__((ext_vector_type(16)));
+constexpr int RM_CS = 8;                  // sites per chunk
+constexpr int RM_ROWS = RM_CS * 6;        // rows per chirality and chunk
+constexpr int RM_LD = 33;                 // padded row length (float2) in LDS
+constexpr int RESTRICT_MFMA_MIN_RHS = 16;  // fewer rhs: the VALU kernel (an MFMA tile holds 32)
+
+template <typename S>
+__global__ __launch_bounds__(256) void restrict_mfma_kernel(cx<float>* __restrict__ out, size_t ostr_r, size_t ostr_b,
+                                                            const cx<float>* __restrict__ y, size_t ystr,
+                                                            BasisView<S> bv, Geom g, int nrhs, int face_mu) {
+  __shared__ float2 Ws[2][RM_ROWS][RM_LD];  // [h][row][a]
+  __shared__ float2 Ys[2][RM_ROWS][RM_LD];  // [h][row][rhs]
+  __shared__ float red[2][2][16][64];       // [h][re, im][register][lane] of the upper half waves
+  const int ci = blockIdx.x;
+  const int col0 = blockIdx.y * 32;
+  const int l = threadIdx.x, lane = l & 63, w = l >> 6;
+  const int h = w >> 1, kh = w & 1;
+  const int ntv = g.ntv;
+  const int ncol = min(32, nrhs - col0);
+  const size_t V = g.V;
+  const size_t base = (size_t)ci * g.vblock;
+  const int nsites = face_mu < 0 ? g.vblock : g.vblock / g.bs[face_mu];
+  // padding columns stay zero
+  for (int e = l; e < 2 * RM_ROWS * RM_LD; e += 256) {
+    (&Ws[0][0][0])[e] = make_float2(0.f, 0.f);
+    (&Ys[0][0][0])[e] = make_float2(0.f, 0.f);
+  }
+  mf_v16 RR, II, RI, IR;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) RR[v] = II[v] = RI[v] = IR[v] = 0.f;
+  const int a = lane & 31, kk = lane >> 5;
+  const int nW = 12 * ntv * RM_CS, nY = 12 * ncol * RM_CS;
+  // basis: element (a, comp, site), rhs: element (rhs, comp, site), the
+  // site fastest.  The loads of chunk f0 + RM_CS are issued (unconditionally,
+  // at clamped addresses) before the MFMAs consume chunk f0 from LDS; masks
+  // and scales are applied when the values are stored to LDS.
+  constexpr int NQ = (12 * 32 * RM_CS + 255) / 256;
+  cx<float> wraw[NQ], yraw[NQ];
+  float sraw[NQ];
+  auto fetch = [&](int f0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = l + 256 * q;
+      const int xl = e % RM_CS, rest = e / RM_CS, comp = rest % 12, idx = rest / 12;
+      const int f = min(f0 + xl, nsites - 1);
+      const size_t x = base + (face_mu < 0 ? f : face_site(g, face_mu, g.bs[face_mu] - 1, f));
+      const int ia = min(idx, ntv - 1), ir = min(idx, ncol - 1);
+      wraw[q] = ldc<float>(bv.W, ((size_t)ia * 12 + comp) * V + x);
+      if constexpr (is_half<S>()) sraw[q] = bv.Wsc[(size_t)ia * V + x];
+      yraw[q] = y[(size_t)(col0 + ir) * ystr + (size_t)comp * V + x];
+    }
+  };
+  fetch(0);
+  for (int f0 = 0; f0 < nsites; f0 += RM_CS) {
+    __syncthreads();  // previous chunk consumed (and the zero fill done)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = l + 256 * q;
+      const int xl = e % RM_CS, rest = e / RM_CS, comp = rest % 12, idx = rest / 12;
+      const bool fin = f0 + xl < nsites;
+      float sc = 1.f;
+      if constexpr (is_half<S>()) sc = sraw[q];
+      const float2 wv = fin ? make_float2(sc * wraw[q].r, sc * wraw[q].i) : make_float2(0.f, 0.f);
+      const float2 yv = fin ? make_float2(yraw[q].r, yraw[q].i) : make_float2(0.f, 0.f);
+      if (e < nW) Ws[comp / 6][xl * 6 + comp % 6][idx] = wv;
+      if (e < nY) Ys[comp / 6][xl * 6 + comp % 6][idx] = yv;
+    }
+    if (f0 + RM_CS < nsites) fetch(f0 + RM_CS);
+    __syncthreads();
+    // rows 2t, 2t+1 of chirality h; this wave takes half of the chunk
+#pragma unroll
+    for (int t = kh * (RM_ROWS / 4); t < (kh + 1) * (RM_ROWS / 4); ++t) {
+      const float2 wv = Ws[h][2 * t + kk][a];
+      const float2 yv = Ys[h][2 * t + kk][a];
+      RR = __builtin_amdgcn_mfma_f32_32x32x2f32(wv.x, yv.x, RR, 0, 0, 0);
+      II = __builtin_amdgcn_mfma_f32_32x32x2f32(wv.y, yv.y, II, 0, 0, 0);
+      RI = __builtin_amdgcn_mfma_f32_32x32x2f32(wv.x, yv.y, RI, 0, 0, 0);
+      IR = __builtin_amdgcn_mfma_f32_32x32x2f32(wv.y, yv.x, IR, 0, 0, 0);
+    }
+  }
+  if (kh == 1) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      red[h][0][v][lane] = RR[v] + II[v];
+      red[h][1][v][lane] = RI[v] - IR[v];
+    }
+  }
+  __syncthreads();
+  if (kh == 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int ai = 8 * (v / 4) + 4 * kk + (v % 4);
+      const int r = lane & 31;
+      if (ai < ntv && r < ncol)
+        out[(size_t)(col0 + r) * ostr_r + (size_t)ci * ostr_b + h * ntv + ai] =
+            mk(RR[v] + II[v] + red[h][0][v][lane], RI[v] - IR[v] + red[h][1][v][lane]);
+    }
   }
 }
 
@@ -459,10 +579,17 @@ __global__ void coarse_to_canonical_kernel(cx<double>* canon, const cx<T>* in, G
 
 template <typename T, typename S>
 void launch_restrict(cx<T>* out, size_t ostr_r, size_t ostr_b, const cx<T>* y, size_t ystr, const BasisView<S>& bv,
-                     const Geom& g, int nrhs, hipStream_t st) {
+                     const Geom& g, int nrhs, hipStream_t st, int face_mu) {
   if (nrhs <= 0) return;
+  if constexpr (std::is_same<T, float>::value) {
+    if (nrhs >= RESTRICT_MFMA_MIN_RHS) {
+      dim3 grid(g.nblocks, (nrhs + 31) / 32);
+      restrict_mfma_kernel<S><<<grid, 256, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, nrhs, face_mu);
+      return;
+    }
+  }
   const int threads = ((g.vblock + 63) / 64) * 64;
-  restrict_kernel<T, S><<<g.nblocks, threads, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, nrhs);
+  restrict_kernel<T, S><<<g.nblocks, threads, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, nrhs, face_mu);
 }
 
 template <typename T, typename S>
@@ -549,7 +676,7 @@ void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& 
 
 #define INST_TS(T, S)                                                                                               \
   template void launch_restrict<T, S>(cx<T>*, size_t, size_t, const cx<T>*, size_t, const BasisView<S>&,            \
-                                      const Geom&, int, hipStream_t);                                                \
+                                      const Geom&, int, hipStream_t, int);                                           \
   template void launch_prolong<T, S>(cx<T>*, size_t, const cx<T>*, size_t, const BasisView<S>&, const Geom&, int,    \
                                      hipStream_t);                                                                   \
   template void launch_coarse_stencil<T, S>(cx<T>*, size_t, int, int, const cx<T>*, size_t, const cx<T>*, size_t,    \

@@ -36,14 +36,20 @@ __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out,
   const int wl = xcd_swizzle(blockIdx.x, gridDim.x);
   const int r = wl % nrhs;
   const int ls = (wl / nrhs) * blockDim.x + threadIdx.x;  // lexicographic-block order
-  if (ls >= g.V) return;
-  const int bl = ls / g.vblock;
+  // the block-crossing pieces only touch one layer of every block: one
+  // thread per site of that layer (the output elsewhere is left alone)
+  constexpr bool CROSS = MODE == DS_CROSS_FWD || MODE == DS_CROSS_BWD;
+  const int per_block = CROSS ? g.vblock / g.bs[mu_sel] : g.vblock;
+  if (ls >= g.nblocks * per_block) return;
+  const int bl = ls / per_block;
+  const int lo = ls - bl * per_block;
   int bc[4];
   bc[0] = bl % g.NB[0];
   bc[1] = (bl / g.NB[0]) % g.NB[1];
   bc[2] = (bl / (g.NB[0] * g.NB[1])) % g.NB[2];
   bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
-  const int s = block_to_int(g, bc) * g.vblock + (ls - bl * g.vblock);
+  const int s = block_to_int(g, bc) * g.vblock +
+                (CROSS ? face_site(g, mu_sel, MODE == DS_CROSS_FWD ? g.bs[mu_sel] - 1 : 0, lo) : lo);
   const cx<Tin>* ip = in + (size_t)r * in_rs;
   cx<Tout>* op = out + (size_t)r * out_rs;
   const size_t V = g.V;
@@ -71,7 +77,9 @@ template <typename Tin, typename Tout, typename S, typename Tc>
 void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mode,
                    int mu, int chi_in, size_t in_rstride, size_t out_rstride, hipStream_t st) {
   if (nrhs <= 0) return;
-  const unsigned grid = (unsigned)((g.V + TPB - 1) / TPB) * (unsigned)nrhs;
+  const size_t nsite = (mode == DS_CROSS_FWD || mode == DS_CROSS_BWD) ? (size_t)g.nblocks * (g.vblock / g.bs[mu])
+                                                                      : (size_t)g.V;
+  const unsigned grid = (unsigned)((nsite + TPB - 1) / TPB) * (unsigned)nrhs;
   switch (mode) {
     case DS_FULL:
       dslash_kernel<Tin, Tout, S, Tc, DS_FULL><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride, nrhs);

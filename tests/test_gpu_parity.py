@@ -105,7 +105,7 @@ def test_coarse_operator_restrict_prolong(case, prec):
     dd = _gpu()
     L, block, eps, m0, ntv = CASES[case]
     say("coarse operator", case, "prec", prec)
-    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, max_rhs=17)
     A = dirac.clover_term(U, m0, 1.0)
     blk, W = _basis(L, block, ntv)
     ctx.import_basis(dev(W))
@@ -119,6 +119,11 @@ def test_coarse_operator_restrict_prolong(case, prec):
     yc = torch.zeros((2, nb, 2, ntv), dtype=torch.complex128, device="cuda")
     ctx.mg_restrict(yc, dev(y), 2)
     assert rel(host(yc), coarse.restrict(blk, W, y)) <= TOL[prec]
+    # seventeen rhs: the matrix-core restriction (FP32 paths)
+    y9 = synth.gaussian_spinors(L, 17, 33)
+    yc9 = torch.zeros((17, nb, 2, ntv), dtype=torch.complex128, device="cuda")
+    ctx.mg_restrict(yc9, dev(y9), 17)
+    assert rel(host(yc9), coarse.restrict(blk, W, y9)) <= TOL[prec]
     xc = synth.gaussian_coarse(nb, ntv, 2, 32)
     x = torch.zeros_like(dev(y))
     ctx.mg_prolong(x, dev(xc), 2)
@@ -129,6 +134,25 @@ def test_coarse_operator_restrict_prolong(case, prec):
     nbr = coarse.neighbour_table(blk)
     ref = coarse.coarse_apply(Dc_ref, nbr, xc.reshape(2, nb, n)).reshape(xc.shape)
     assert rel(host(out), ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_coarse_operator_many_test_vectors(prec):
+    """ntv = 20 (at least 16 columns per Galerkin pass): D_c assembled with
+    the matrix-core restriction, summing the block-crossing pieces over the
+    last layer of each block only, matches the oracle."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = (4, 4, 4, 4), (2, 2, 2, 2), 0.3, -0.1, 20
+    say("coarse operator ntv 20 prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    A = dirac.clover_term(U, m0, 1.0)
+    blk, W = _basis(L, block, ntv)
+    ctx.import_basis(dev(W))
+    nb, n = blk.nblocks, 2 * ntv
+    Dc_ref = coarse.coarse_operator(U, A, blk, W)
+    Dc = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
+    ctx.export_coarse(Dc)
+    assert rel(host(Dc), Dc_ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("case", ["c1_4x4x4x4", "ragged_6x4x4x4"])

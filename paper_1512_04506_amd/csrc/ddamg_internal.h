@@ -84,6 +84,22 @@ __device__ inline cx<T> ldc(const __half2* p, size_t i) {
   float2 f = __half22float2(p[i]);
   return mk((T)f.x, (T)f.y);
 }
+// Element i < 2^28 of a field plane whose base is wave-uniform: the byte
+// offset is formed in 32 bits, so the load takes the scalar-base +
+// 32-bit-offset form instead of a 64-bit address per lane and load.
+template <typename X>
+__device__ inline const X& elem(const X* p, unsigned i) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(p) + i * (unsigned)sizeof(X));
+}
+template <typename T>
+__device__ inline cx<T> ldc(const cx<double>* p, unsigned i) { cx<double> v = elem(p, i); return mk((T)v.r, (T)v.i); }
+template <typename T>
+__device__ inline cx<T> ldc(const cx<float>* p, unsigned i) { cx<float> v = elem(p, i); return mk((T)v.r, (T)v.i); }
+template <typename T>
+__device__ inline cx<T> ldc(const __half2* p, unsigned i) {
+  float2 f = __half22float2(elem(p, i));
+  return mk((T)f.x, (T)f.y);
+}
 template <typename T>
 __device__ inline T ldr(const double* p, size_t i) { return (T)p[i]; }
 template <typename T>

@@ -77,7 +77,7 @@ __device__ inline void load_spinor(cx<Tc> p[4][3], const cx<Tin>* in, int s, siz
     const bool keep = !CHI || chi_in < 0 || (sp >> 1) == chi_in;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cx<Tc> v = cvt<Tc>(in[(size_t)(3 * sp + c) * V + s]);
+      cx<Tc> v = cvt<Tc>(elem(in + (size_t)(3 * sp + c) * V, (unsigned)s));
       p[sp][c] = keep ? sign * v : mk((Tc)0, (Tc)0);
     }
   }
@@ -90,7 +90,7 @@ __device__ inline void load_link(cx<Tc> u[3][3], const GaugeView<S>& gv, int mu,
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[a][b] = ldc<Tc>(gv.U, (size_t)(mu * 9 + 3 * a + b) * V + s);
+    for (int b = 0; b < 3; ++b) u[a][b] = ldc<Tc>(gv.U + (size_t)(mu * 9 + 3 * a + b) * V, (unsigned)s);
 }
 
 // acc += -1/2 (1 -+ g_mu) [U_mu(slink) or U_mu(slink)^dag] p
@@ -162,7 +162,7 @@ __device__ inline void clover_apply(cx<Tc> acc[4][3], const cx<Tc> p[4][3], cons
     cx<Tc> o[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const cx<Tc> d = ldc<Tc>(Ah, (size_t)k * V + s);
+      const cx<Tc> d = ldc<Tc>(Ah + (size_t)k * V, (unsigned)s);
       o[2 * k] = d.r * v[2 * k];
       o[2 * k + 1] = d.i * v[2 * k + 1];
     }
@@ -171,7 +171,7 @@ __device__ inline void clover_apply(cx<Tc> acc[4][3], const cx<Tc> p[4][3], cons
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = i + 1; j < 6; ++j) {
-        const cx<Tc> a = ldc<Tc>(Ah, (size_t)(3 + q) * V + s);
+        const cx<Tc> a = ldc<Tc>(Ah + (size_t)(3 + q) * V, (unsigned)s);
         o[i] = cfma(a, v[j], o[i]);
         o[j] = cfmac(a, v[i], o[j]);
         ++q;
@@ -192,7 +192,7 @@ __device__ inline void clover_apply_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[N
     const stc_t<S>* Ah = gv.A + (size_t)h * CLOVER_PAIRS * V;
     cx<Tc> a[CLOVER_PAIRS];
 #pragma unroll
-    for (int e = 0; e < CLOVER_PAIRS; ++e) a[e] = ldc<Tc>(Ah, (size_t)e * V + s);
+    for (int e = 0; e < CLOVER_PAIRS; ++e) a[e] = ldc<Tc>(Ah + (size_t)e * V, (unsigned)s);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       cx<Tc> v[6], o[6];

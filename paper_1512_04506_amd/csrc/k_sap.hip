@@ -20,10 +20,28 @@ namespace {
 
 using namespace dev;
 
+// Sum over the 64 lanes of a wave by DPP lane moves (no LDS round trips):
+// quad sums, then row sums (lanes 15, 31, 47, 63), then the row broadcasts;
+// lane 63 ends with the total.
+template <int CTRL, int ROWS>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 template <typename T>
-__device__ inline T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+__device__ inline T wave_sum63(T v) {
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -142,7 +160,7 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
       for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          rho[r][sp][k] = y[(size_t)min(r, nr - 1) * rs + (size_t)(3 * sp + k) * V + s] - acc[r][sp][k];
+          rho[r][sp][k] = elem(y + (size_t)min(r, nr - 1) * rs + (size_t)(3 * sp + k) * V, (unsigned)s) - acc[r][sp][k];
   }
 
   for (int it = 0; it < n_mr; ++it) {
@@ -197,8 +215,8 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T v = wave_sum(dots[r][c]);
-        if ((l & 63) == 0) red[w * 3 * NR + 3 * r + c] = v;
+        const T v = wave_sum63(dots[r][c]);
+        if ((l & 63) == 63) red[w * 3 * NR + 3 * r + c] = v;
       }
     __syncthreads();
 #pragma unroll
@@ -209,7 +227,8 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
         a_im += red[k * 3 * NR + 3 * r + 1];
         n2 += red[k * 3 * NR + 3 * r + 2];
       }
-      const cx<T> alpha = n2 > (T)0 ? mk(a_re / n2, a_im / n2) : mk((T)0, (T)0);
+      const T inv = n2 > (T)0 ? (T)1 / n2 : (T)0;
+      const cx<T> alpha = mk(a_re * inv, a_im * inv);
       if (act) {
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)

@@ -120,6 +120,18 @@ void ddamg_default_params(ddamg_params* p);
  * not NULL, writes a NUL-terminated reason into msg[0..msg_len-1]. */
 int ddamg_validate_params(const ddamg_params* p, char* msg, size_t msg_len);
 
+/* Device allocator for the workspace of contexts created afterwards
+ * (process-wide; alloc == NULL and free_fn == NULL restore hipMalloc /
+ * hipFree).  alloc(bytes, user) returns device memory or NULL (the call
+ * that needed it then fails with DDAMG_ENOMEM); every block is released
+ * with the free_fn(ptr, user) that was installed when it was allocated,
+ * after the device has finished all work queued before the release.
+ * For callers that own device memory themselves, e.g. a framework's caching
+ * allocator.  DDAMG_EARG if exactly one of alloc and free_fn is NULL. */
+typedef void* (*ddamg_alloc_fn)(size_t bytes, void* user);
+typedef void (*ddamg_free_fn)(void* ptr, void* user);
+int ddamg_set_allocator(ddamg_alloc_fn alloc, ddamg_free_fn free_fn, void* user);
+
 /* Creates a context on the current HIP device.  gauge: canonical links
  * (device, complex128), copied; the clover term A(x) is built from them
  * (Alg. 7 names its blocks C^{hh}(x)) and all storage precisions are
@@ -153,8 +165,24 @@ int ddamg_export_basis(ddamg_ctx* ctx, double* W);
 /* Exports the setup's current test vectors (FP64, canonical [ntv][V][4][3]). */
 int ddamg_export_tv(ddamg_ctx* ctx, double* tv);
 
+/* Takes tv (device, complex128 [ntv][V][4][3], e.g. from ddamg_export_tv of
+ * a context with the same parameters) as the setup's test vectors and
+ * builds R (the Gram-Schmidt of Alg. 5 on every aggregate) and D_c = R D P
+ * from them, without smoothing: resumes a saved setup state.  Synchronous;
+ * DDAMG_ENUMERIC for a rank-deficient aggregate. */
+int ddamg_import_tv(ddamg_ctx* ctx, const double* tv);
+
 /* Exports D_c (Eq. cgo), dequantised, as [Nblock][9][2ntv][2ntv] complex128. */
 int ddamg_export_coarse(ddamg_ctx* ctx, double* Dc);
+
+/* Replaces D_c by Dc (device, complex128, the layout ddamg_export_coarse
+ * writes: block lexicographic, slots self, +x, -x, ..., +t, -t, each block
+ * row-major) and prepares the coarse solve from it (storage precision of
+ * the context, inverse of the even self blocks).  The basis is kept, so a
+ * setup (mg_setup, ddamg_import_basis or ddamg_import_tv) must precede it
+ * (DDAMG_ESTATE).  Synchronous; DDAMG_ENUMERIC for a singular even self
+ * block. */
+int ddamg_import_coarse(ddamg_ctx* ctx, const double* Dc);
 
 /* Exports the clover term A(x) in FP64 as [V][2][6][6] complex128. */
 int ddamg_export_clover(ddamg_ctx* ctx, double* A);

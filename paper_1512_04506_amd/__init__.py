@@ -25,7 +25,8 @@ EXPORTS = (
     "mg_setup", "ddamg_import_basis", "ddamg_export_basis", "ddamg_export_tv", "ddamg_export_coarse",
     "ddamg_export_clover", "mg_apply", "dirac_apply", "coarse_apply", "mg_restrict", "mg_prolong", "solve",
     "ddamg_get_stats", "ddamg_reset_stats", "dirac_apply_internal", "coarse_apply_internal", "ddamg_volume",
-    "ddamg_nblocks", "ddamg_set_kernel_timing", "ddamg_get_kernel_times",
+    "ddamg_nblocks", "ddamg_set_kernel_timing", "ddamg_get_kernel_times", "ddamg_import_tv",
+    "ddamg_import_coarse", "ddamg_set_allocator",
 )
 KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
                 "setup_galerkin", "residual")
@@ -62,6 +63,10 @@ class Stats(ctypes.Structure):
         return d
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libddamg.so is not built (run paper_1512_04506_amd/build.py); "
@@ -79,6 +84,9 @@ def _load():
         "ddamg_export_basis": (i32, [vp, dp]),
         "ddamg_export_tv": (i32, [vp, dp]),
         "ddamg_export_coarse": (i32, [vp, dp]),
+        "ddamg_import_tv": (i32, [vp, dp]),
+        "ddamg_import_coarse": (i32, [vp, dp]),
+        "ddamg_set_allocator": (i32, [ALLOC_FN, FREE_FN, vp]),
         "ddamg_export_clover": (i32, [vp, dp]),
         "mg_apply": (i32, [vp, dp, dp, i32]),
         "dirac_apply": (i32, [vp, dp, dp, i32, i32]),
@@ -104,6 +112,27 @@ def _load():
 
 
 lib = _load()
+
+
+_allocator_refs = []  # every installed pair stays alive: buffers free through the pair they came from
+
+
+def set_allocator(alloc=None, free=None):
+    """ddamg_set_allocator: alloc(nbytes) -> device address (int, 0 on
+    failure) and free(address) own the workspace of contexts created from
+    now on; set_allocator() restores hipMalloc / hipFree.  Both are called
+    from the library's thread while it holds no Python state."""
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must both be given or both be None")
+    if alloc is None:
+        rc = lib.ddamg_set_allocator(ALLOC_FN(), FREE_FN(), None)
+    else:
+        a = ALLOC_FN(lambda n, user: alloc(int(n)) or None)
+        f = FREE_FN(lambda ptr, user: free(int(ptr)))
+        _allocator_refs.append((a, f))
+        rc = lib.ddamg_set_allocator(a, f, None)
+    if rc != 0:
+        raise DDAMGError(rc, lib.ddamg_last_error(None).decode())
 
 
 def default_params(**kw):
@@ -204,6 +233,13 @@ class Context:
     def export_coarse(self, Dc):
         n = self.nblocks * 9 * (2 * self.ntv) ** 2 * 16
         return self._check(lib.ddamg_export_coarse(self.h, _ptr(Dc, "Dc", n)))
+
+    def import_tv(self, tv):
+        return self._check(lib.ddamg_import_tv(self.h, _ptr(tv, "tv", self.fine_bytes(self.ntv))))
+
+    def import_coarse(self, Dc):
+        n = self.nblocks * 9 * (2 * self.ntv) ** 2 * 16
+        return self._check(lib.ddamg_import_coarse(self.h, _ptr(Dc, "Dc", n)))
 
     def export_clover(self, A):
         return self._check(lib.ddamg_export_clover(self.h, _ptr(A, "A", self.V * 72 * 16)))

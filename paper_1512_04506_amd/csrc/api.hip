@@ -40,26 +40,20 @@ inline void check_launch(const char* what) {
   if (e != hipSuccess) throw Fail{DDAMG_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-template <typename X>
-X* dalloc(size_t n) {
-  if (n == 0) n = 1;
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, n * sizeof(X));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Fail{DDAMG_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(X)) + " bytes failed"};
-  }
-  return static_cast<X*>(p);
-}
+// Workspace allocator: hipMalloc / hipFree unless the caller installed a
+// hook; every buffer remembers the release function it was allocated with.
+ddamg_alloc_fn g_alloc = nullptr;
+ddamg_free_fn g_free = nullptr;
+void* g_alloc_user = nullptr;
 
 struct DevBuf {
   void* p = nullptr;
+  ddamg_free_fn fr = nullptr;  // nullptr: hipFree
+  void* user = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
+  ~DevBuf() { release(); }
   template <typename X>
   X* get() const {
     return static_cast<X*>(p);
@@ -67,14 +61,44 @@ struct DevBuf {
   template <typename X>
   X* alloc(size_t n) {
     release();
-    p = dalloc<X>(n);
+    const size_t bytes = (n == 0 ? 1 : n) * sizeof(X);
+    if (g_alloc) {
+      p = g_alloc(bytes, g_alloc_user);
+      if (!p) throw Fail{DDAMG_ENOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes"};
+      fr = g_free;
+      user = g_alloc_user;
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        throw Fail{DDAMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+      }
+      fr = nullptr;
+      user = nullptr;
+    }
     return get<X>();
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (fr) {
+        // hipFree waits for the device; a hook need not, so wait here (rare:
+        // buffers change only at setup, first solves and destruction)
+        (void)hipDeviceSynchronize();
+        fr(p, user);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
+    fr = nullptr;
+    user = nullptr;
   }
-  void swap(DevBuf& o) { std::swap(p, o.p); }
+  void swap(DevBuf& o) {
+    std::swap(p, o.p);
+    std::swap(fr, o.fr);
+    std::swap(user, o.user);
+  }
 };
 
 std::string g_create_error;
@@ -214,6 +238,8 @@ struct SolverBase {
   virtual void import_basis(const double* W) = 0;
   virtual void export_basis(double* W) = 0;
   virtual void export_tv(double* tv) = 0;
+  virtual void import_tv(const double* tv) = 0;
+  virtual void import_coarse(const double* Dc) = 0;
   virtual void export_coarse(double* Dc) = 0;
   virtual void vcycle_canon(double* x, const double* y, int nrhs) = 0;
   virtual void coarse_canon(double* out, const double* in, int nrhs) = 0;
@@ -575,6 +601,24 @@ struct Solver final : SolverBase {
     launch_dequantize_basis<double, S>(W, bv(), g, st);
     launch_spinor_to_canonical<double>(reinterpret_cast<cx<double>*>(Wc), W, g, g.ntv, st);
     c->sync();
+  }
+  void import_tv(const double* tvc) override {
+    launch_spinor_to_internal<T>(tv.get<cx<T>>(), reinterpret_cast<const cx<double>*>(tvc), g, g.ntv, st);
+    build_coarse();
+    c->sync();
+  }
+  void import_coarse(const double* Dc) override {
+    ensure_setup_ws();
+    cx<T>* D = ws_D.get<cx<T>>();
+    launch_coarse_import<T>(D, reinterpret_cast<const cx<double>*>(Dc), g, st);
+    launch_quantize_coarse<T, S>(Dq.get<stc_t<S>>(), Dsc.get<float>(), D, g, st);
+    HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
+    launch_invert_even_blocks<T, S>(Dinv.get<cx<T>>(), cv(), g, c->status.get<int>(), st);
+    check_launch("import coarse");
+    int stat = 0;
+    HIPCK(hipMemcpyAsync(&stat, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    c->sync();
+    if (stat) throw Fail{DDAMG_ENUMERIC, "singular even self-coupling block of D_c"};
   }
   void export_tv(double* out) override {
     launch_spinor_to_canonical<T>(reinterpret_cast<cx<double>*>(out), tv.get<cx<T>>(), g, g.ntv, st);
@@ -1082,6 +1126,44 @@ int ddamg_export_tv(ddamg_ctx* c, double* tv) {
   c->sol->export_tv(tv);
   return DDAMG_OK;
   GUARD_END
+}
+
+int ddamg_import_tv(ddamg_ctx* c, const double* tv) {
+  if (!c) return DDAMG_EARG;
+  if (!tv) {
+    c->err = "tv is NULL";
+    return DDAMG_EARG;
+  }
+  GUARD_BEGIN
+  c->setup_done = false;
+  c->sol->import_tv(tv);
+  c->setup_done = true;
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_import_coarse(ddamg_ctx* c, const double* Dc) {
+  if (!c) return DDAMG_EARG;
+  if (!Dc) {
+    c->err = "Dc is NULL";
+    return DDAMG_EARG;
+  }
+  if (int e = need_setup(c)) return e;
+  GUARD_BEGIN
+  c->sol->import_coarse(Dc);
+  return DDAMG_OK;
+  GUARD_END
+}
+
+int ddamg_set_allocator(ddamg_alloc_fn alloc, ddamg_free_fn free_fn, void* user) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    g_create_error = "ddamg_set_allocator: alloc and free_fn must both be set or both be NULL";
+    return DDAMG_EARG;
+  }
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_user = alloc ? user : nullptr;
+  return DDAMG_OK;
 }
 
 int ddamg_export_coarse(ddamg_ctx* c, double* Dc) {

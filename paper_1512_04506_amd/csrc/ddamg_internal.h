@@ -297,6 +297,9 @@ template <typename T, typename S>
 void launch_dequantize_basis(cx<T>* out, const BasisView<S>& bv, const Geom& g, hipStream_t st);
 template <typename T>
 void launch_dagger_fill(cx<T>* Dc, const int* nbr, const Geom& g, hipStream_t st);
+// D_c in the exported layout -> internal accumulation layout
+template <typename T>
+void launch_coarse_import(cx<T>* D, const cx<double>* in, const Geom& g, hipStream_t st);
 template <typename T, typename S>
 void launch_quantize_coarse(stc_t<S>* Dq, float* Dsc, const cx<T>* Dc, const Geom& g, hipStream_t st);
 template <typename T, typename S>

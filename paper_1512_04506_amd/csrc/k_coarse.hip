@@ -542,6 +542,22 @@ __global__ void export_coarse_kernel(cx<double>* out, CoarseView<S> cv, Geom g) 
   }
 }
 
+// D_c from the exported layout (block lexicographic, row-major blocks) into
+// the internal one (internal block order, column-major blocks)
+template <typename T>
+__global__ void coarse_import_kernel(cx<T>* D, const cx<double>* in, Geom g) {
+  const int ci = blockIdx.x, slot = blockIdx.y;
+  const int nc = g.nc;
+  int bc[4];
+  int_block_coords(g, ci, bc);
+  const int b = lex_block(g, bc);
+  const size_t nn = (size_t)nc * nc;
+  for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
+    const int col = e / nc, row = e % nc;
+    D[((size_t)ci * 9 + slot) * nn + e] = cvt<T>(in[((size_t)b * 9 + slot) * nn + (size_t)row * nc + col]);
+  }
+}
+
 __device__ inline int lex_to_int_block(const Geom& g, int b) {
   int bc[4];
   bc[0] = b % g.NB[0]; b /= g.NB[0];
@@ -664,6 +680,11 @@ void launch_export_coarse(cx<double>* out, const CoarseView<S>& cv, const Geom& 
 }
 
 template <typename T>
+void launch_coarse_import(cx<T>* D, const cx<double>* in, const Geom& g, hipStream_t st) {
+  coarse_import_kernel<T><<<dim3(g.nblocks, 9), 256, 0, st>>>(D, in, g);
+}
+
+template <typename T>
 void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * g.nblocks * g.nc;
   if (n) coarse_to_internal_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, canon, g, nrhs);
@@ -694,6 +715,7 @@ INST_TS(float, __half)
   template void launch_block_matvec<T>(cx<T>*, size_t, const cx<T>*, const cx<T>*, size_t, int, int, int,            \
                                        hipStream_t);                                                                 \
   template void launch_dagger_fill<T>(cx<T>*, const int*, const Geom&, hipStream_t);                                 \
+  template void launch_coarse_import<T>(cx<T>*, const cx<double>*, const Geom&, hipStream_t);                        \
   template void launch_coarse_to_internal<T>(cx<T>*, const cx<double>*, const Geom&, int, hipStream_t);              \
   template void launch_coarse_to_canonical<T>(cx<double>*, const cx<T>*, const Geom&, int, hipStream_t);
 INST_T(double)

@@ -14,6 +14,7 @@ HEADER = os.path.join(ROOT, "include", "ddamg.h")
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"^\s*typedef[^;]*;", "", src, flags=re.M)  # function-pointer types are not entry points
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
@@ -95,3 +96,20 @@ def test_create_rejects_before_any_hip_call(dd):
     assert lib.coarse_apply(None, None, None, 1) == -1
     assert lib.mg_apply(None, None, None, 1) == -1
     assert lib.ddamg_volume(None) == -1
+
+
+def test_set_allocator_arguments(dd):
+    """Exactly one of the two hooks NULL is rejected; both NULL restores
+    the default (no GPU involved)."""
+    a = dd.ALLOC_FN(lambda n, user: None)
+    assert dd.lib.ddamg_set_allocator(a, dd.FREE_FN(), None) == -1
+    assert b"both" in dd.lib.ddamg_last_error(None)
+    assert dd.lib.ddamg_set_allocator(dd.ALLOC_FN(), dd.FREE_FN(), None) == 0
+    with pytest.raises(ValueError):
+        dd.set_allocator(lambda n: 0, None)
+    dd.set_allocator()
+
+
+def test_import_rejects_null_and_missing_setup(dd):
+    assert dd.lib.ddamg_import_tv(None, None) == -1
+    assert dd.lib.ddamg_import_coarse(None, None) == -1

@@ -285,3 +285,92 @@ def test_errors_before_setup_and_bad_args():
     with pytest.raises(dd.DDAMGError) as e:
         ctx.dirac_apply(y, y, 1)
     assert e.value.code == -1
+
+
+def test_import_tv_resumes_setup():
+    """ddamg_export_tv of a finished setup, given to a fresh context through
+    ddamg_import_tv, reproduces its D_c (same test vectors, same kernels)."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    say("import tv")
+    ctx1, U = make_ctx(dd, L, block, eps, m0, ntv, 2)
+    ctx1.mg_setup(dev(synth.gaussian_spinors(L, ntv, 77)))
+    tv = torch.zeros((ntv,) + tuple(reversed(L)) + (4, 3), dtype=torch.complex128, device="cuda").reshape(ntv, -1)
+    ctx1.export_tv(tv)
+    nb, n = ctx1.nblocks, 2 * ntv
+    D1 = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
+    ctx1.export_coarse(D1)
+    ctx2, _ = make_ctx(dd, L, block, eps, m0, ntv, 2)
+    ctx2.import_tv(tv)
+    D2 = torch.zeros_like(D1)
+    ctx2.export_coarse(D2)
+    assert rel(host(D2), host(D1)) <= 1e-12
+    f = synth.gaussian_spinors(L, 1, 78)
+    u = torch.zeros_like(dev(f))
+    rc, st = ctx2.solve(u, dev(f), 1, 1e-10)
+    assert rc == 0
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_import_coarse_injection(prec):
+    """A D_c injected with ddamg_import_coarse (the oracle's) is the one
+    coarse_apply uses; before any setup the call is refused."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["ragged_6x4x4x4"]
+    say("import coarse prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    A = dirac.clover_term(U, m0, 1.0)
+    blk, W = _basis(L, block, ntv)
+    nb, n = blk.nblocks, 2 * ntv
+    Dc_ref = coarse.coarse_operator(U, A, blk, W)
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.import_coarse(dev(Dc_ref))
+    assert e.value.code == -2
+    ctx.import_basis(dev(W))
+    # perturb the self blocks so the injected operator differs from the built one
+    Dc_inj = Dc_ref.copy()
+    Dc_inj[:, 0] *= 1.25
+    ctx.import_coarse(dev(Dc_inj))
+    xc = synth.gaussian_coarse(nb, ntv, 2, 79)
+    out = torch.zeros_like(dev(xc))
+    ctx.coarse_apply(out, dev(xc), 2)
+    nbr = coarse.neighbour_table(blk)
+    ref = coarse.coarse_apply(Dc_inj, nbr, xc.reshape(2, nb, n)).reshape(xc.shape)
+    assert rel(host(out), ref) <= TOL[prec]
+
+
+def test_allocator_hook_owns_workspace():
+    """With a caller's allocator installed (here torch's caching
+    allocator), a context allocates through it and releases every block on
+    destruction; the default is restored afterwards."""
+    dd = _gpu()
+    live = {}
+
+    def alloc(n):
+        p = torch.cuda.caching_allocator_alloc(n)
+        live[p] = n
+        return p
+
+    def free(p):
+        assert p in live
+        del live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    say("allocator hook")
+    dd.set_allocator(alloc, free)
+    try:
+        ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 2)
+        ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 80)))
+        f = synth.gaussian_spinors(L, 1, 81)
+        u = torch.zeros_like(dev(f))
+        rc, st = ctx.solve(u, dev(f), 1, 1e-10)
+        assert rc == 0
+        assert len(live) > 0
+        ctx.close()
+        assert len(live) == 0
+    finally:
+        dd.set_allocator()
+    A = dirac.clover_term(U, m0, 1.0)
+    res = f[0] - dirac.apply_D(U, A, host(u)[0])
+    assert np.linalg.norm(res) / np.linalg.norm(f[0]) <= 1e-10

@@ -36,7 +36,8 @@ WORKLOADS = {
 # record names the sources it was taken from and is ignored once they change
 TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic_32x32x32x64.txt")
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (counts packed dual FP32 issue)
+FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz: the library is built without packed FP32
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -191,6 +192,9 @@ def dominant_roofline(w, kt, prec):
            "frac": r["achieved"] / r["peak"], "traffic": None,
            "avg_launch_ms": r["ms"] / r["launches"], "launches": r["launches"],
            "algorithmic_per_launch": r["per_launch"]}
+    if kind == "sap" and prec != 0:
+        out["peak_unpacked"] = FP32_UNPACKED_TFLOPS
+        out["frac_unpacked"] = r["achieved"] / FP32_UNPACKED_TFLOPS
     return out
 
 

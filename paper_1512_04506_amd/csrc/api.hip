@@ -306,11 +306,12 @@ struct Solver final : SolverBase {
   // setup workspace, allocated at the first setup and kept: FP64 copy of
   // the test vectors for the Gram-Schmidt, dequantised basis, D_c
   // accumulation buffer and one chunk of D_ij P_j columns
-  DevBuf ws_Wd, ws_Wt, ws_D, ws_Z;
+  DevBuf ws_Wd, ws_Wt, ws_D, ws_Z, ws_T;
   static constexpr int GAL_CHUNK = 32;  // all test vectors of one chirality per pass
   void ensure_setup_ws() {
     if (ws_Wd.p) return;
     ws_Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
+    ws_T.alloc<cx<double>>((size_t)2 * g.nblocks * QR_TWS_PER_AGG);
     if (is_half<S>()) ws_Wt.alloc<cx<T>>((size_t)g.ntv * fsz());  // else the stored basis is already cx<T>
     ws_D.alloc<cx<T>>((size_t)g.nblocks * 9 * g.nc * g.nc);
     ws_Z.alloc<cx<T>>((size_t)std::min(g.ntv, GAL_CHUNK) * fsz());
@@ -556,7 +557,7 @@ struct Solver final : SolverBase {
     cx<double>* W = ws_Wd.get<cx<double>>();
     launch_copy<double, T>(W, fsz(), tv.get<cx<T>>(), fsz(), fsz(), g.ntv, st);
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
-    c->timed(DDAMG_KERNEL_SETUP_QR, g.ntv, [&] { launch_aggregate_qr(W, g, c->status.get<int>(), st); });
+    c->timed(DDAMG_KERNEL_SETUP_QR, g.ntv, [&] { launch_aggregate_qr(W, g, c->status.get<int>(), ws_T.get<cx<double>>(), st); });
     check_launch("aggregate qr");
     int stat = 0;
     HIPCK(hipMemcpyAsync(&stat, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));

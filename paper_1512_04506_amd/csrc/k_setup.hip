@@ -17,7 +17,9 @@ namespace {
 
 constexpr int QR_THREADS = 256;
 constexpr int MAX_NTV = 32;
-constexpr int QR_U = 4;  // 4-row slices per load round of the Gram matrix
+constexpr int QR_CS = 8;             // sites per staged chunk of the Gram matrix pass
+constexpr int QR_ROWS = QR_CS * 6;   // rows (site, spin-colour) per chunk
+constexpr int QR_LD = MAX_NTV + 1;   // padded LDS row
 // One workgroup per aggregate (internal block ci, chirality h): rows are the
 // 6 V_block (spin of chirality h x colour, site) entries, columns the ntv
 // test vectors.  Per CholQR pass:
@@ -32,10 +34,18 @@ constexpr int QR_U = 4;  // 4-row slices per load round of the Gram matrix
 //              in place).
 typedef double qr_v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W, Geom g, int* status) {
+__global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<double>* W, Geom g, int* status,
+                                                             cx<double>* Tinv) {
   __shared__ cx<double> G[MAX_NTV][MAX_NTV];
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];  // T^{-1}, upper triangular
-  __shared__ qr_v4d part[2][6][64];            // partial tiles of two waves
+  // the staged rows of the Gram matrix pass, later the partial tiles of two
+  // waves
+  constexpr size_t STAGE_BYTES = sizeof(cx<double>) * QR_ROWS * QR_LD > sizeof(qr_v4d) * 2 * 6 * 64
+                                     ? sizeof(cx<double>) * QR_ROWS * QR_LD
+                                     : sizeof(qr_v4d) * 2 * 6 * 64;
+  __shared__ __attribute__((aligned(32))) char stage_raw[STAGE_BYTES];
+  auto Xs = reinterpret_cast<cx<double>(*)[QR_LD]>(stage_raw);
+  auto part = reinterpret_cast<qr_v4d(*)[6][64]>(stage_raw);
   __shared__ int fail;
   const int ci = blockIdx.x >> 1;  // internal block: its sites are ci * vblock + [0, vblock)
   const int h = blockIdx.x & 1;
@@ -46,51 +56,66 @@ __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W,
   const bool act = l < vb;
   const size_t site = (size_t)ci * vb + (act ? l : 0);
   const size_t base = (size_t)ci * vb;
-  auto X = [&](int a, int k) -> cx<double>* { return W + ((size_t)a * 12 + 6 * h + k) * V + site; };
   const bool two = n > 16;           // second column tile (columns 16..31)
-  const int nsteps = (6 * vb + 3) / 4;  // 4-row slices
   const int col0 = lane & 15, rsub = lane >> 4;
-  const int a0 = min(col0, n - 1), a1 = min(16 + col0, n - 1);
-  const double m0 = col0 < n ? 1.0 : 0.0, m1 = 16 + col0 < n ? 1.0 : 0.0;
-  for (int pass = 0; pass < 2; ++pass) {
+  {
     // tiles: 0 = Re(0,0) 1 = Im(0,0) 2 = Re(0,1) 3 = Im(0,1) 4 = Re(1,1) 5 = Im(1,1)
     qr_v4d acc[6];
 #pragma unroll
     for (int t = 0; t < 6; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
-    // QR_U slices per round: all loads of a round are issued before its
-    // MFMAs, so a wave has 2 QR_U loads in flight instead of 2
-    for (int s0 = w; s0 < nsteps; s0 += 4 * QR_U) {
-      cx<double> x0[QR_U], x1[QR_U];
+    // Rows (site, spin-colour) of QR_CS sites at a time are staged in LDS
+    // with coalesced loads (QR_CS consecutive sites of one test vector and
+    // component per 128-byte line); the next chunk's loads are in flight
+    // while the MFMAs consume the current one.
+    constexpr int NQ = QR_ROWS * 32 / 256;
+    cx<double> xq[NQ];
+    auto fetch = [&](int s0) {
 #pragma unroll
-      for (int u = 0; u < QR_U; ++u) {
-        const int row = 4 * (s0 + 4 * u) + rsub;
-        const bool live = row < 6 * vb;
-        const int c = live ? row / vb : 0, sr = live ? row % vb : 0;
-        const double mr = live ? 1.0 : 0.0;
-        const cx<double>* xp = W + (size_t)(6 * h + c) * V + base + sr;
-        x0[u] = (mr * m0) * xp[(size_t)a0 * 12 * V];
-        if (two) x1[u] = (mr * m1) * xp[(size_t)a1 * 12 * V];
+      for (int q = 0; q < NQ; ++q) {
+        const int e = l + 256 * q;
+        const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
+        const int sx = min(s0 + sl, vb - 1), ax = min(a, n - 1);
+        xq[q] = W[((size_t)ax * 12 + 6 * h + c) * V + base + sx];
       }
+    };
+    fetch(0);
+    for (int s0 = 0; s0 < vb; s0 += QR_CS) {
+      __syncthreads();  // the previous chunk has been consumed
 #pragma unroll
-      for (int u = 0; u < QR_U; ++u) {
-        const cx<double> y0 = x0[u];
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
+      for (int q = 0; q < NQ; ++q) {
+        const int e = l + 256 * q;
+        const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
+        Xs[sl * 6 + c][a] = (s0 + sl < vb && a < n) ? xq[q] : mk(0.0, 0.0);
+      }
+      if (s0 + QR_CS < vb) fetch(s0 + QR_CS);
+      __syncthreads();
+      // 4-row slices; the two products feeding one accumulator are issued
+      // apart so no MFMA waits on the one before it
+      for (int t = w; t < QR_ROWS / 4; t += 4) {
+        const cx<double> y0 = Xs[4 * t + rsub][col0];
         if (two) {
-          const cx<double> y1 = x1[u];
+          const cx<double> y1 = Xs[4 * t + rsub][16 + col0];
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
           acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.r, acc[2], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y1.i, acc[2], 0, 0, 0);
           acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.i, acc[3], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y1.r, acc[3], 0, 0, 0);
           acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.r, acc[4], 0, 0, 0);
-          acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.i, y1.i, acc[4], 0, 0, 0);
           acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.i, acc[5], 0, 0, 0);
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y1.i, acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y1.r, acc[3], 0, 0, 0);
+          acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.i, y1.i, acc[4], 0, 0, 0);
           acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1.i, y1.r, acc[5], 0, 0, 0);
+        } else {
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
         }
       }
     }
+    __syncthreads();  // the staging buffer is reused for the partial tiles
     // sum the four waves' tiles: waves 2,3 hand theirs to waves 0,1, then
     // wave 1 to wave 0, which writes G (upper triangle and the (1,0) tile
     // never read)
@@ -146,6 +171,8 @@ __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W,
     __syncthreads();
     if (fail) {
       if (l == 0) atomicExch(status, 1);
+      cx<double>* To = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
+      for (int e = l; e < n * n; e += blockDim.x) To[e] = mk(0.0, 0.0);
       return;
     }
     // T^{-1} by back substitution, one column per lane
@@ -153,37 +180,62 @@ __global__ __launch_bounds__(QR_THREADS) void aggregate_qr_kernel(cx<double>* W,
       const int j = l;
       for (int i = j + 1; i < n; ++i) Ti[i][j] = mk(0.0, 0.0);
       Ti[j][j] = mk(1.0 / G[j][j].r, 0.0);
+#pragma unroll 1
       for (int i = j - 1; i >= 0; --i) {
         cx<double> vv = mk(0.0, 0.0);
+#pragma unroll 1
         for (int mm = i + 1; mm <= j; ++mm) vv = cfma(G[i][mm], Ti[mm][j], vv);
         Ti[i][j] = (-1.0 / G[i][i].r) * vv;
       }
     }
     __syncthreads();
-    // X <- X T^{-1}: lane = site, one row (spin-colour k) at a time; each
-    // input entry is read once and added into every output it feeds, and the
-    // row is written back after all its entries have been read
-    if (act) {
-      for (int k = 0; k < 6; ++k) {
-        cx<double> y[MAX_NTV];
-#pragma unroll
-        for (int j = 0; j < MAX_NTV; ++j) y[j] = mk(0.0, 0.0);
-#pragma unroll
-        for (int i = 0; i < MAX_NTV; ++i) {
-          if (i < n) {
-            const cx<double> xi = *X(i, k);
-#pragma unroll
-            for (int j = i; j < MAX_NTV; ++j)
-              if (j < n) y[j] = cfma(xi, Ti[i][j], y[j]);
-          }
-          if ((i & 3) == 3) asm volatile("" ::: "memory");  // bound the loads in flight
-        }
-#pragma unroll
-        for (int j = 0; j < MAX_NTV; ++j)
-          if (j < n) *X(j, k) = y[j];
-      }
-    }
+    // T^{-1} of this aggregate for the update kernel (zero on failure)
+    cx<double>* To = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
+    for (int e = l; e < n * n; e += blockDim.x) To[e] = Ti[e / n][e % n];
     __syncthreads();
+  }
+}
+
+// X <- X T^{-1} on one aggregate: lane = site, T^{-1} (upper triangular)
+// read from the Gram kernel's output into LDS and used as broadcasts.
+__global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* W, Geom g, const cx<double>* Tinv) {
+  __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];
+  const int ci = blockIdx.x >> 1;
+  const int h = blockIdx.x & 1;
+  const int n = g.ntv;
+  const size_t V = g.V;
+  const int l = threadIdx.x;
+  const bool act = l < g.vblock;
+  const bool two = n > 16;
+  const size_t site = (size_t)ci * g.vblock + (act ? l : 0);
+  const cx<double>* Tg = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
+  for (int e = l; e < n * n; e += blockDim.x) Ti[e / n][e % n] = Tg[e];
+  __syncthreads();
+  if (!act) return;
+  auto X = [&](int a, int k) -> cx<double>* { return W + ((size_t)a * 12 + 6 * h + k) * V + site; };
+  for (int k = 0; k < 6; ++k) {
+    // output columns in two halves of 16, so that 16 accumulators are
+    // live: columns 16..31 first (for n > 16; they read every input row),
+    // then 0..15, which read only rows 0..15, not yet overwritten.  Each
+    // lane reads and writes only its own site.
+    for (int jh = two ? 1 : 0; jh >= 0; --jh) {
+      cx<double> y[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) y[j] = mk(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < MAX_NTV; ++i) {
+        if (i < n && i < 16 * jh + 16) {
+          const cx<double> xi = *X(i, k);
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (16 * jh + j >= i && 16 * jh + j < n) y[j] = cfma(xi, Ti[i][16 * jh + j], y[j]);
+        }
+        if ((i & 3) == 3) asm volatile("" ::: "memory");  // bound the loads in flight
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (16 * jh + j < n) *X(16 * jh + j, k) = y[j];
+    }
   }
 }
 
@@ -224,8 +276,11 @@ __global__ void dequantize_basis_kernel(cx<T>* out, BasisView<S> bv, int V, int 
 
 }  // namespace
 
-void launch_aggregate_qr(cx<double>* W, const Geom& g, int* status, hipStream_t st) {
-  aggregate_qr_kernel<<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, status);
+void launch_aggregate_qr(cx<double>* W, const Geom& g, int* status, cx<double>* tws, hipStream_t st) {
+  for (int pass = 0; pass < 2; ++pass) {  // CholQR2
+    qr_gram_kernel<<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, status, tws);
+    qr_update_kernel<<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, tws);
+  }
 }
 
 template <typename S>

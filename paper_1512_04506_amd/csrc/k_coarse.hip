@@ -172,7 +172,10 @@ __global__ __launch_bounds__(256) void restrict_mfma_kernel(cx<float>* __restric
                                                             BasisView<S> bv, Geom g, int nrhs, int face_mu) {
   __shared__ float2 Ws[2][RM_ROWS][RM_LD];  // [h][row][a]
   __shared__ float2 Ys[2][RM_ROWS][RM_LD];  // [h][row][rhs]
-  __shared__ float red[2][2][16][64];       // [h][re, im][register][lane] of the upper half waves
+  // [h][re, im][register][lane] of the upper-half waves, in the basis
+  // staging area once the chunks are done (three workgroups fit a CU)
+  static_assert(sizeof(float) * 2 * 2 * 16 * 64 <= sizeof(float2) * 2 * RM_ROWS * RM_LD, "reduction area");
+  auto red = reinterpret_cast<float(*)[2][16][64]>(&Ws[0][0][0]);
   const int ci = blockIdx.x;
   const int col0 = blockIdx.y * 32;
   const int l = threadIdx.x, lane = l & 63, w = l >> 6;
@@ -240,6 +243,7 @@ __global__ __launch_bounds__(256) void restrict_mfma_kernel(cx<float>* __restric
       IR = __builtin_amdgcn_mfma_f32_32x32x2f32(wv.y, yv.x, IR, 0, 0, 0);
     }
   }
+  __syncthreads();  // every wave is done with the staging area
   if (kh == 1) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -310,13 +314,16 @@ __global__ __launch_bounds__(256) void prolong_kernel(cx<T>* __restrict__ x, siz
 
 // ------------------------------------------------------------ D_c stencil
 // One workgroup per (output coarse site, group of RB right-hand sides).
-// Thread (row, cg) accumulates the columns col = cg (mod CG) of every slot;
-// each slot's input vectors are staged in LDS (read as broadcasts), and the
-// CG partial sums of a row are combined through LDS at the end.
+// Thread (row group, cg) accumulates RP consecutive rows over the columns
+// col = cg (mod CG) of every slot, so each input value read from LDS (a
+// broadcast) feeds RP rows; each slot's input vectors are staged in LDS,
+// and the CG partial sums of a row are combined through LDS at the end.
+// RP = 2 for few rhs (the D_c stream), 1 for 12 rhs (the partial sums of
+// two rows would cost occupancy).
 //   out = add + cs D_self xs + cn sum_{slot>0} D_slot xn(nbr)
 // With Dmat != nullptr the kernel instead computes out = Dmat[k] x[k] for
 // dense column-major per-site matrices (the even-site D_ee^{-1}).
-template <typename T, typename S, int RB>
+template <typename T, typename S, int RB, int RP>
 __global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__ out, size_t ostr, int out_first,
                                                              const cx<T>* __restrict__ add, size_t astr,
                                                              const cx<T>* __restrict__ xs, size_t xsstr, int xs_first,
@@ -330,12 +337,16 @@ __global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__
   const int r0 = blockIdx.y * RB;
   const int nr = min(RB, nrhs - r0);
   const int t = threadIdx.x;
-  const int row = t % nc, cg = t / nc;
+  const int ngr = nc / RP;  // nc = 2 ntv is even
+  const int rg = t % ngr, cg = t / ngr;
   const bool act = cg < CG;
+  const int row = RP * rg;
   const size_t nn = (size_t)nc * nc;
-  cx<T> acc[RB];
+  cx<T> acc[RP][RB];
 #pragma unroll
-  for (int j = 0; j < RB; ++j) acc[j] = mk((T)0, (T)0);
+  for (int q = 0; q < RP; ++q)
+#pragma unroll
+    for (int j = 0; j < RB; ++j) acc[q][j] = mk((T)0, (T)0);
   const int s_beg = Dmat ? 0 : (cs != (T)0 ? 0 : 1);
   const int s_end = Dmat ? 1 : (cn != (T)0 ? 9 : 1);
   for (int slot = s_beg; slot < s_end; ++slot) {
@@ -354,21 +365,24 @@ __global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__
     }
     __syncthreads();
     if (act) {
-      if (Dmat) {
-        const cx<T>* Mk = Dmat + (size_t)(ci - out_first) * nn + row;
-        for (int col = cg; col < nc; col += CG) {
-          const cx<T> d = Mk[(size_t)col * nc];
+      for (int col = cg; col < nc; col += CG) {
+        cx<T> d[RP];
+        if (Dmat) {
+          const cx<T>* Mk = Dmat + (size_t)(ci - out_first) * nn + (size_t)col * nc + row;
 #pragma unroll
-          for (int j = 0; j < RB; ++j)
-            if (j < nr) acc[j] = acc[j] + d * xl[col * RB + j];
+          for (int q = 0; q < RP; ++q) d[q] = Mk[q];
+        } else {
+          const size_t base = ((size_t)ci * 9 + slot) * nn + (size_t)col * nc + row;
+#pragma unroll
+          for (int q = 0; q < RP; ++q) d[q] = coef * ldc<T>(cv.D, base + q);
         }
-      } else {
-        const size_t base = ((size_t)ci * 9 + slot) * nn + row;
-        for (int col = cg; col < nc; col += CG) {
-          const cx<T> d = coef * ldc<T>(cv.D, base + (size_t)col * nc);
 #pragma unroll
-          for (int j = 0; j < RB; ++j)
-            if (j < nr) acc[j] = acc[j] + d * xl[col * RB + j];
+        for (int j = 0; j < RB; ++j) {
+          if (j < nr) {
+            const cx<T> xj = xl[col * RB + j];
+#pragma unroll
+            for (int q = 0; q < RP; ++q) acc[q][j] = acc[q][j] + d[q] * xj;
+          }
         }
       }
     }
@@ -376,7 +390,9 @@ __global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__
   __syncthreads();
   if (act)
 #pragma unroll
-    for (int j = 0; j < RB; ++j) xl[((size_t)cg * nc + row) * RB + j] = acc[j];
+    for (int q = 0; q < RP; ++q)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) xl[((size_t)cg * nc + row + q) * RB + j] = acc[q][j];
   __syncthreads();
   for (int e = t; e < nc * nr; e += blockDim.x) {
     const int rw = e / nr, j = e % nr;
@@ -623,21 +639,24 @@ void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T
                     const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr, int xn_first,
                     T cn, const CoarseView<S>& cv, const cx<T>* Dmat, int nc, int nrhs, hipStream_t st) {
   if (nrhs <= 0 || nout <= 0) return;
-  const int CG = nc >= 256 ? 1 : 256 / nc;
-  const int threads = CG * nc;
+  // CG column groups of nc / RP row groups (at most 256 threads), fewer if
+  // the CG partial sums of RB rhs would not fit 64 KB of LDS
+  auto cg_for = [&](int rb, int rp) {
+    const int cg = std::max(1, 256 * rp / nc);
+    const int cap = (int)(65536 / ((size_t)nc * rb * sizeof(cx<T>)));
+    return std::max(1, std::min(cg, cap));
+  };
   if (nrhs == 1) {
-    const size_t lds = (size_t)CG * nc * 1 * sizeof(cx<T>);
-    coarse_stencil_kernel<T, S, 1><<<dim3(nout, 1), threads, lds, st>>>(out, ostr, out_first, add, astr, xs, xsstr,
-                                                                        xs_first, cs, xn, xnstr, xn_first, cn, cv,
-                                                                        Dmat, nc, CG, nrhs);
+    const int CG = cg_for(1, 2);
+    coarse_stencil_kernel<T, S, 1, 2><<<dim3(nout, 1), CG * (nc / 2), (size_t)CG * nc * sizeof(cx<T>), st>>>(
+        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
   } else if (nrhs <= 4) {
-    const size_t lds = (size_t)CG * nc * 4 * sizeof(cx<T>);
-    coarse_stencil_kernel<T, S, 4><<<dim3(nout, 1), threads, lds, st>>>(out, ostr, out_first, add, astr, xs, xsstr,
-                                                                        xs_first, cs, xn, xnstr, xn_first, cn, cv,
-                                                                        Dmat, nc, CG, nrhs);
+    const int CG = cg_for(4, 2);
+    coarse_stencil_kernel<T, S, 4, 2><<<dim3(nout, 1), CG * (nc / 2), (size_t)CG * nc * 4 * sizeof(cx<T>), st>>>(
+        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
   } else {
-    const size_t lds = (size_t)CG * nc * 12 * sizeof(cx<T>);
-    coarse_stencil_kernel<T, S, 12><<<dim3(nout, (nrhs + 11) / 12), threads, lds, st>>>(
+    const int CG = cg_for(12, 1);
+    coarse_stencil_kernel<T, S, 12, 1><<<dim3(nout, (nrhs + 11) / 12), CG * nc, (size_t)CG * nc * 12 * sizeof(cx<T>), st>>>(
         out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
   }
 }

@@ -354,7 +354,7 @@ struct Solver final : SolverBase {
     Dq.alloc<stc_t<S>>((size_t)g.nblocks * 9 * g.nc * g.nc);
     if (is_half<S>()) Dsc.alloc<float>((size_t)g.nblocks * 9);
     Dinv.alloc<cx<T>>((size_t)g.neven * g.nc * g.nc);
-    tv.alloc<cx<T>>((size_t)g.ntv * fsz());
+    tv.alloc<cx<T>>((size_t)maxr * fsz());  // as large as fy: the setup swaps the two
     fy.alloc<cx<T>>((size_t)maxr * fsz());
     fx.alloc<cx<T>>((size_t)maxr * fsz());
     yc.alloc<cx<T>>((size_t)maxr * csz());
@@ -555,9 +555,11 @@ struct Solver final : SolverBase {
   void build_coarse() {
     ensure_setup_ws();
     cx<double>* W = ws_Wd.get<cx<double>>();
-    launch_copy<double, T>(W, fsz(), tv.get<cx<T>>(), fsz(), fsz(), g.ntv, st);
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
-    c->timed(DDAMG_KERNEL_SETUP_QR, g.ntv, [&] { launch_aggregate_qr(W, g, c->status.get<int>(), ws_T.get<cx<double>>(), st); });
+    // the first CholQR pass reads the test vectors in their own precision and
+    // writes the FP64 copy W, the second works on W in place
+    c->timed(DDAMG_KERNEL_SETUP_QR, g.ntv,
+             [&] { launch_aggregate_qr<T>(W, tv.get<cx<T>>(), g, c->status.get<int>(), ws_T.get<cx<double>>(), st); });
     check_launch("aggregate qr");
     int stat = 0;
     HIPCK(hipMemcpyAsync(&stat, c->status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -570,9 +572,12 @@ struct Solver final : SolverBase {
     const int n = g.ntv;
     cx<T>* V = tv.get<cx<T>>();
     launch_spinor_to_internal<T>(V, reinterpret_cast<const cx<double>*>(tv_canon), g, n, st);
-    // initial setup: smoother with N_smoother = 1, 2, 3 from a zero guess
+    // initial setup: smoother with N_smoother = 1, 2, 3 from a zero guess;
+    // the current vectors move to fy (a buffer swap, no copy) and the
+    // result is built in tv
     for (int k = 1; k <= 3; ++k) {
-      launch_copy<T, T>(fy.get<cx<T>>(), fsz(), V, fsz(), fsz(), n, st);
+      tv.swap(fy);
+      V = tv.get<cx<T>>();
       HIPCK(hipMemsetAsync(V, 0, sizeof(cx<T>) * fsz() * n, st));
       sap(V, fy.get<cx<T>>(), n, k);
     }
@@ -580,7 +585,8 @@ struct Solver final : SolverBase {
     normalise(V, n);
     // iterative setup: every test vector replaced by the V-cycle applied to it
     for (int i = 0; i < c->p.n_setup; ++i) {
-      launch_copy<T, T>(fy.get<cx<T>>(), fsz(), V, fsz(), fsz(), n, st);
+      tv.swap(fy);
+      V = tv.get<cx<T>>();
       vcycle(V, fy.get<cx<T>>(), n);
       normalise(V, n);
       build_coarse();

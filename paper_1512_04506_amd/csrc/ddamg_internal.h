@@ -292,7 +292,11 @@ void launch_block_matvec(cx<T>* out, size_t ostr, const cx<T>* M, const cx<T>* x
 // setup kernels
 // tws: workspace of 2 nblocks * QR_TWS_PER_AGG complex doubles (T^{-1} per aggregate)
 constexpr int QR_TWS_PER_AGG = 32 * 32;
-void launch_aggregate_qr(cx<double>* W, const Geom& g, int* status, cx<double>* tws, hipStream_t st);
+// Orthonormalises the test vectors X (precision Tin) on every aggregate into
+// the FP64 basis W (CholQR2; status set to 1 for a rank-deficient aggregate)
+template <typename Tin>
+void launch_aggregate_qr(cx<double>* W, const cx<Tin>* X, const Geom& g, int* status, cx<double>* tws,
+                         hipStream_t st);
 template <typename S>
 void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st);
 template <typename T, typename S>

@@ -34,7 +34,8 @@ constexpr int QR_LD = MAX_NTV + 1;   // padded LDS row
 //              in place).
 typedef double qr_v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<double>* W, Geom g, int* status,
+template <typename Tin>
+__global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, Geom g, int* status,
                                                              cx<double>* Tinv) {
   __shared__ cx<double> G[MAX_NTV][MAX_NTV];
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];  // T^{-1}, upper triangular
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<double>* W
         const int e = l + 256 * q;
         const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
         const int sx = min(s0 + sl, vb - 1), ax = min(a, n - 1);
-        xq[q] = W[((size_t)ax * 12 + 6 * h + c) * V + base + sx];
+        xq[q] = cvt<double>(W[((size_t)ax * 12 + 6 * h + c) * V + base + sx]);
       }
     };
     fetch(0);
@@ -196,9 +197,12 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<double>* W
   }
 }
 
-// X <- X T^{-1} on one aggregate: lane = site, T^{-1} (upper triangular)
-// read from the Gram kernel's output into LDS and used as broadcasts.
-__global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* W, Geom g, const cx<double>* Tinv) {
+// Wout <- Xin T^{-1} on one aggregate (in place when Wout == Xin): lane =
+// site, T^{-1} (upper triangular) read from the Gram kernel's output into
+// LDS and used as broadcasts.
+template <typename Tin>
+__global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* Wout, const cx<Tin>* Xin, Geom g,
+                                                               const cx<double>* Tinv) {
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];
   const int ci = blockIdx.x >> 1;
   const int h = blockIdx.x & 1;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* W, Ge
   for (int e = l; e < n * n; e += blockDim.x) Ti[e / n][e % n] = Tg[e];
   __syncthreads();
   if (!act) return;
-  auto X = [&](int a, int k) -> cx<double>* { return W + ((size_t)a * 12 + 6 * h + k) * V + site; };
+  auto idx = [&](int a, int k) -> size_t { return ((size_t)a * 12 + 6 * h + k) * V + site; };
   for (int k = 0; k < 6; ++k) {
     // output columns in two halves of 16, so that 16 accumulators are
     // live: columns 16..31 first (for n > 16; they read every input row),
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* W, Ge
 #pragma unroll
       for (int i = 0; i < MAX_NTV; ++i) {
         if (i < n && i < 16 * jh + 16) {
-          const cx<double> xi = *X(i, k);
+          const cx<double> xi = cvt<double>(Xin[idx(i, k)]);
 #pragma unroll
           for (int j = 0; j < 16; ++j)
             if (16 * jh + j >= i && 16 * jh + j < n) y[j] = cfma(xi, Ti[i][16 * jh + j], y[j]);
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* W, Ge
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        if (16 * jh + j < n) *X(16 * jh + j, k) = y[j];
+        if (16 * jh + j < n) Wout[idx(16 * jh + j, k)] = y[j];
     }
   }
 }
@@ -246,18 +250,19 @@ __global__ void quantize_basis_kernel(stc_t<S>* Wq, float* Wsc, const cx<double>
   const int s = (int)(idx % V);
   const int a = (int)(idx / V);
   if constexpr (is_half<S>()) {
+    cx<double> v[12];  // one read of the 12 entries: max, then the scaled copy
     double m = 0.0;
+#pragma unroll
     for (int k = 0; k < 12; ++k) {
-      cx<double> v = W[((size_t)a * 12 + k) * V + s];
-      m = fmax(m, fmax(fabs(v.r), fabs(v.i)));
+      v[k] = W[((size_t)a * 12 + k) * V + s];
+      m = fmax(m, fmax(fabs(v[k].r), fabs(v[k].i)));
     }
     const float fm = (float)m;
     Wsc[idx] = fm;
     const double inv = fm > 0.f ? 1.0 / (double)fm : 0.0;
-    for (int k = 0; k < 12; ++k) {
-      cx<double> v = W[((size_t)a * 12 + k) * V + s];
-      Wq[((size_t)a * 12 + k) * V + s] = __floats2half2_rn((float)(v.r * inv), (float)(v.i * inv));
-    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      Wq[((size_t)a * 12 + k) * V + s] = __floats2half2_rn((float)(v[k].r * inv), (float)(v[k].i * inv));
   } else {
     for (int k = 0; k < 12; ++k) stc_store(Wq, ((size_t)a * 12 + k) * V + s, W[((size_t)a * 12 + k) * V + s]);
   }
@@ -276,12 +281,18 @@ __global__ void dequantize_basis_kernel(cx<T>* out, BasisView<S> bv, int V, int 
 
 }  // namespace
 
-void launch_aggregate_qr(cx<double>* W, const Geom& g, int* status, cx<double>* tws, hipStream_t st) {
-  for (int pass = 0; pass < 2; ++pass) {  // CholQR2
-    qr_gram_kernel<<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, status, tws);
-    qr_update_kernel<<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, tws);
-  }
+template <typename Tin>
+void launch_aggregate_qr(cx<double>* W, const cx<Tin>* X, const Geom& g, int* status, cx<double>* tws,
+                         hipStream_t st) {
+  // CholQR2: pass 1 from X into W, pass 2 on W in place
+  qr_gram_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(X, g, status, tws);
+  qr_update_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, X, g, tws);
+  qr_gram_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, status, tws);
+  qr_update_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, W, g, tws);
 }
+template void launch_aggregate_qr<double>(cx<double>*, const cx<double>*, const Geom&, int*, cx<double>*,
+                                          hipStream_t);
+template void launch_aggregate_qr<float>(cx<double>*, const cx<float>*, const Geom&, int*, cx<double>*, hipStream_t);
 
 template <typename S>
 void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st) {

@@ -136,14 +136,17 @@ def test_coarse_operator_restrict_prolong(case, prec):
     assert rel(host(out), ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("geom", [((4, 4, 4, 4), (2, 2, 2, 2), 20), ((8, 4, 4, 4), (4, 2, 2, 2), 16)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_coarse_operator_many_test_vectors(prec):
-    """ntv = 20 (at least 16 columns per Galerkin pass): D_c assembled with
+def test_coarse_operator_many_test_vectors(prec, geom):
+    """ntv >= 16 (at least 16 columns per Galerkin pass): D_c assembled with
     the matrix-core restriction, summing the block-crossing pieces over the
-    last layer of each block only, matches the oracle."""
+    last layer of each block only, matches the oracle.  Blocks 4 wide in x
+    take the four-site vector staging on every face but x."""
     dd = _gpu()
-    L, block, eps, m0, ntv = (4, 4, 4, 4), (2, 2, 2, 2), 0.3, -0.1, 20
-    say("coarse operator ntv 20 prec", prec)
+    L, block, ntv = geom
+    eps, m0 = 0.3, -0.1
+    say("coarse operator", L, block, "ntv", ntv, "prec", prec)
     ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
     A = dirac.clover_term(U, m0, 1.0)
     blk, W = _basis(L, block, ntv)

@@ -191,3 +191,62 @@ def apply_B(U, A, psi, L, block):
     (Dirichlet truncation), i.e. the couplings within blocks of Alg. 3."""
     in_fwd, in_bwd, _, _ = block_hop_masks(L, block)
     return apply_clover(A, psi) - 0.5 * hopping(U, psi, in_fwd, in_bwd)
+
+
+def _wrap(c, L):
+    return tuple(int(c[i]) % L[i] for i in range(4))
+
+
+def apply_D_sites(U, m0, csw, psi, sites):
+    """(D psi)(x) at the listed sites only (the same operator as apply_D,
+    computed site by site from its definition: clover term from the four
+    leaves at x, then the eight hops with the sign on the t wrap).  For
+    sampled checks on lattices too large for the full-field routines.
+
+    sites: integer array (n, 4) of (x, y, z, t); returns (n, 4, 3)."""
+    Lt, Lz, Ly, Lx = U.shape[:4]
+    L = (Lx, Ly, Lz, Lt)
+
+    def link(mu, c):
+        x, y, z, t = _wrap(c, L)
+        return U[t, z, y, x, mu]
+
+    def field(c):
+        x, y, z, t = c
+        sign = -1.0 if (t < 0 or t >= Lt) else 1.0
+        x, y, z, t = _wrap(c, L)
+        return sign * psi[t, z, y, x]
+
+    def step(c, mu, d):
+        e = list(c)
+        e[mu] += d
+        return e
+
+    out = np.zeros((len(sites), 4, 3), dtype=np.complex128)
+    for n, c0 in enumerate(np.asarray(sites)):
+        c = [int(v) for v in c0]
+        A = (4.0 + m0) * np.eye(12, dtype=np.complex128)
+        if csw != 0.0:
+            for mu in range(4):
+                for nu in range(4):
+                    if mu == nu:
+                        continue
+                    pm, pn, mm, mn = step(c, mu, 1), step(c, nu, 1), step(c, mu, -1), step(c, nu, -1)
+                    q = link(mu, c) @ link(nu, pm) @ _dag(link(mu, pn)) @ _dag(link(nu, c))
+                    q = q + link(nu, c) @ _dag(link(mu, step(pn, mu, -1))) @ _dag(link(nu, mm)) @ link(mu, mm)
+                    q = q + (_dag(link(mu, mm)) @ _dag(link(nu, step(mm, nu, -1))) @ link(mu, step(mm, nu, -1))
+                             @ link(nu, mn))
+                    q = q + _dag(link(nu, mn)) @ link(mu, mn) @ link(nu, step(mn, mu, 1)) @ _dag(link(mu, c))
+                    F = (q - _dag(q)) / 8.0
+                    sig = 0.5j * (GAMMA[mu] @ GAMMA[nu] - GAMMA[nu] @ GAMMA[mu])
+                    A += csw * 0.25j * np.kron(sig, F)
+        v = A @ psi[c[3] % Lt, c[2] % Lz, c[1] % Ly, c[0] % Lx].reshape(12)
+        hop = np.zeros((4, 3), dtype=np.complex128)
+        for mu in range(4):
+            f = field(step(c, mu, 1))
+            a = f @ link(mu, c).T                 # U_mu(x) psi(x+mu), colour index last
+            hop += a - GAMMA[mu] @ a
+            b = field(step(c, mu, -1)) @ np.conj(link(mu, step(c, mu, -1)))  # U_mu(x-mu)^dag psi(x-mu)
+            hop += b + GAMMA[mu] @ b
+        out[n] = v.reshape(4, 3) - 0.5 * hop
+    return out

@@ -18,6 +18,7 @@
 
 #include "../../include/ddamg.h"
 #include "ddamg_internal.h"
+#include "galerkin.h"
 
 using namespace ddamg;
 
@@ -524,11 +525,17 @@ struct Solver final : SolverBase {
     }
     const int CH = std::min(g.ntv, (int)GAL_CHUNK);
     cx<T>* Zp = ws_Z.get<cx<T>>();
+    // FP32 assembly with up to 32 test vectors: the block-crossing pieces
+    // come from one fused contraction of the basis (no D P field); otherwise
+    // every piece is D applied to the basis, then restricted
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const bool fused_cross = f32 && g.ntv <= GALERKIN_CROSS_MAX_NTV;
+    const int npiece = fused_cross ? 1 : 5;
     for (int hp = 0; hp < 2; ++hp)
       for (int a0 = 0; a0 < g.ntv; a0 += CH) {
         const int na = std::min(CH, g.ntv - a0);
         const cx<T>* in = Wtp + (size_t)a0 * fsz();
-        for (int piece = 0; piece < 5; ++piece) {
+        for (int piece = 0; piece < npiece; ++piece) {
           const int mode = piece == 0 ? DS_BLOCK : DS_CROSS_FWD;
           const int mu = piece == 0 ? 0 : piece - 1;
           const int slot = piece == 0 ? 0 : 1 + 2 * mu;
@@ -540,6 +547,10 @@ struct Solver final : SolverBase {
           });
         }
       }
+    if constexpr (f32) {
+      if (fused_cross)
+        c->timed(DDAMG_KERNEL_SETUP_GALERKIN, 2 * g.ntv, [&] { launch_galerkin_cross<S>(D, bv(), gva, g, st); });
+    }
     launch_dagger_fill<T>(D, c->nbr.get<int>(), g, st);
     launch_quantize_coarse<T, S>(Dq.get<stc_t<S>>(), Dsc.get<float>(), D, g, st);
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));

@@ -4,16 +4,20 @@
 //                                         + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
 //
 // (Sec. 1; the hop/clover structure is the one Alg. 7 applies to the columns
-// of P).  One thread per (site, rhs): consecutive lanes own consecutive
-// sites, so every load of a spinor component, link entry or clover entry is
-// a coalesced 64-lane access.  The spin projectors (1 -+ g_mu) reduce each
-// hop to a 2-spinor (6 complex) before the SU(3) multiply.  In the chiral
-// basis g_mu = [[0, X_mu], [X_mu^dag, 0]] with X_k = -i s_k and X_4 = -1:
+// of P).  One thread per (site, group of NR rhs): consecutive lanes own
+// consecutive sites, so every load of a spinor component, link entry or
+// clover entry is a coalesced 64-lane access, and each link and clover entry
+// loaded is used for all NR right-hand sides held in registers.  The spin
+// projectors (1 -+ g_mu) reduce each hop to a 2-spinor (6 complex) before the
+// SU(3) multiply.  In the chiral basis g_mu = [[0, X_mu], [X_mu^dag, 0]] with
+// X_k = -i s_k and X_4 = -1:
 //   (1 - g) psi = (h, -X^dag h),  h = psi_up - X psi_dn
 //   (1 + g) psi = (h,  X^dag h),  h = psi_up + X psi_dn
 // Variants: the full operator, the block operator B (hops leaving the block
 // dropped, Alg. 3), and the block-crossing forward/backward hops of one
-// direction (the pieces D_ij of Eq. cgo for a neighbour block j).
+// direction (the pieces D_ij of Eq. cgo for a neighbour block j).  The input
+// of the block and crossing variants may be restricted to one chirality
+// (a column of P); the other chirality is then neither loaded nor used.
 // Workgroups walk the blocks in lexicographic order (through the XCD
 // swizzle), so face neighbours are processed at the same time on the same
 // XCD although blocks of opposite parity are far apart in memory.
@@ -26,16 +30,135 @@ namespace {
 constexpr int TPB = 256;
 using namespace dev;
 
-template <typename Tin, typename Tout, typename S, typename Tc, int MODE>
+// spinor of one rhs at site s; with chi >= 0 only the spins of that chirality
+// are loaded (a uniform branch), the others are zero
+template <typename Tin, typename Tc>
+__device__ inline void load_spinor_chi(cx<Tc> p[4][3], const cx<Tin>* in, int s, size_t V, int chi) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    const bool keep = chi < 0 || (sp >> 1) == chi;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (keep)
+        p[sp][c] = cvt<Tc>(elem(in + (size_t)(3 * sp + c) * V, (unsigned)s));
+      else
+        p[sp][c] = mk((Tc)0, (Tc)0);
+    }
+  }
+}
+
+// acc[r] += -1/2 sign (1 -+ g_MU) [U_MU(slink) or its adjoint] psi_r(sn) for
+// the nr rhs of the group (the slots r >= nr read rhs nr - 1 and are never
+// stored), with one load of the link
+template <int MU, bool FWD, int NR, typename Tin, typename Tc, typename S>
+__device__ inline void hop_group(cx<Tc> acc[NR][4][3], const cx<Tin>* in, size_t rs, int nr, const GaugeView<S>& gv,
+                                 int sn, int slink, size_t V, int chi, Tc sign) {
+  cx<Tc> U[3][3];
+  load_link<Tc, S>(U, gv, MU, slink, V);
+  Tc coef = (Tc)-0.5 * sign;
+  if constexpr (is_half<S>()) coef *= (Tc)gv.Usc[slink];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    cx<Tc> p[4][3];
+    load_spinor_chi<Tin, Tc>(p, in + (size_t)min(r, nr - 1) * rs, sn, V, chi);
+    Half2<Tc> h, u;
+    project<MU, FWD, Tc>(h, p);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cx<Tc> t = mk((Tc)0, (Tc)0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t = FWD ? cfma(U[a][b], h.h[sp][b], t) : cfmac(U[b][a], h.h[sp][b], t);
+        u.h[sp][a] = t;
+      }
+    reconstruct<MU, FWD, Tc>(acc[r], u, coef);
+  }
+}
+
+// acc[r] += A(x) psi_r(x), one chirality block at a time (the clover is
+// block diagonal in chirality); a chirality absent from the input is skipped
+template <int NR, typename Tin, typename Tc, typename S>
+__device__ inline void clover_group(cx<Tc> acc[NR][4][3], const cx<Tin>* in, size_t rs, int nr, const GaugeView<S>& gv,
+                                    int s, size_t V, int chi) {
+  Tc sc = (Tc)1;
+  if constexpr (is_half<S>()) sc = (Tc)gv.Asc[s];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (chi >= 0 && h != chi) continue;
+    const stc_t<S>* Ah = gv.A + (size_t)h * CLOVER_PAIRS * V;
+    cx<Tc> a[CLOVER_PAIRS];
+#pragma unroll
+    for (int e = 0; e < CLOVER_PAIRS; ++e) a[e] = ldc<Tc>(Ah + (size_t)e * V, (unsigned)s);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const cx<Tin>* ir = in + (size_t)min(r, nr - 1) * rs;
+      cx<Tc> v[6], o[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] = cvt<Tc>(elem(ir + (size_t)(6 * h + k) * V, (unsigned)s));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        o[2 * k] = a[k].r * v[2 * k];
+        o[2 * k + 1] = a[k].i * v[2 * k + 1];
+      }
+      int q = 0;
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+          o[i] = cfma(a[3 + q], v[j], o[i]);
+          o[j] = cfmac(a[3 + q], v[i], o[j]);
+          ++q;
+        }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[r][2 * h + k / 3][k % 3] = acc[r][2 * h + k / 3][k % 3] + sc * o[k];
+    }
+  }
+}
+
+// the hops of direction MU that MODE selects (see hops_mu in dirac_device.h);
+// a hop across the time boundary carries the factor -1
+template <int MU, int MODE, int NR, typename Tin, typename Tc, typename S>
+__device__ inline void hops_group_mu(cx<Tc> acc[NR][4][3], const cx<Tin>* in, size_t rs, int nr,
+                                     const GaugeView<S>& gv, const Geom& g, const SitePos& p, int mu_sel, int chi) {
+  const size_t V = g.V;
+  const int l = p.lc[MU];
+  bool do_f, do_b;
+  if (MODE == DS_FULL) {
+    do_f = do_b = g.V > 0;  // opaque: keeps every hop in its own branch
+  } else if (MODE == DS_BLOCK) {
+    do_f = l != g.bs[MU] - 1;
+    do_b = l != 0;
+  } else if (MODE == DS_CROSS_FWD) {
+    do_f = MU == mu_sel && l == g.bs[MU] - 1;
+    do_b = false;
+  } else {
+    do_f = false;
+    do_b = MU == mu_sel && l == 0;
+  }
+  if (do_f) {
+    const bool wrap = MU == 3 && l == g.bs[3] - 1 && p.bc[3] == g.NB[3] - 1;
+    hop_group<MU, true, NR, Tin, Tc, S>(acc, in, rs, nr, gv, nbr_fwd(g, p, MU), p.S, V, chi, wrap ? (Tc)-1 : (Tc)1);
+  }
+  if (do_b) {
+    const bool wrap = MU == 3 && l == 0 && p.bc[3] == 0;
+    const int sb = nbr_bwd(g, p, MU);
+    hop_group<MU, false, NR, Tin, Tc, S>(acc, in, rs, nr, gv, sb, sb, V, chi, wrap ? (Tc)-1 : (Tc)1);
+  }
+}
+
+template <typename Tin, typename Tout, typename S, typename Tc, int MODE, int NR>
 __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out, const cx<Tin>* __restrict__ in,
                                                      GaugeView<S> gv, Geom g, int mu_sel, int chi_in, size_t in_rs,
                                                      size_t out_rs, int nrhs) {
-  // workgroup = (run of 256 sites, rhs) with the rhs fastest, so the
-  // workgroups that read the same links and clover run side by side on one
-  // XCD and share its L2
+  // workgroup = (run of 256 sites, group of NR rhs) with the group fastest,
+  // so the workgroups that read the same links and clover run side by side
+  // on one XCD and share its L2
+  const int ngroup = (nrhs + NR - 1) / NR;
   const int wl = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int r = wl % nrhs;
-  const int ls = (wl / nrhs) * blockDim.x + threadIdx.x;  // lexicographic-block order
+  const int r0 = (wl % ngroup) * NR;
+  const int nr = min(NR, nrhs - r0);
+  const int ls = (wl / ngroup) * blockDim.x + threadIdx.x;  // lexicographic-block order
   // the block-crossing pieces only touch one layer of every block: one
   // thread per site of that layer (the output elsewhere is left alone)
   constexpr bool CROSS = MODE == DS_CROSS_FWD || MODE == DS_CROSS_BWD;
@@ -50,25 +173,59 @@ __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out,
   bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
   const int s = block_to_int(g, bc) * g.vblock +
                 (CROSS ? face_site(g, mu_sel, MODE == DS_CROSS_FWD ? g.bs[mu_sel] - 1 : 0, lo) : lo);
-  const cx<Tin>* ip = in + (size_t)r * in_rs;
-  cx<Tout>* op = out + (size_t)r * out_rs;
+  const cx<Tin>* ip = in + (size_t)r0 * in_rs;
+  cx<Tout>* op = out + (size_t)r0 * out_rs;
   const size_t V = g.V;
+  // the full operator takes both chiralities whatever chi_in says
+  const int chi = MODE == DS_FULL ? -1 : chi_in;
   const SitePos pos = site_pos(g, s);
-  cx<Tc> acc[4][3];
+  cx<Tc> acc[NR][4][3];
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
+  for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc[sp][k] = mk((Tc)0, (Tc)0);
-  if (MODE == DS_FULL || MODE == DS_BLOCK) {
-    cx<Tc> p[4][3];
-    load_spinor<Tin, Tc, MODE != DS_FULL>(p, ip, s, V, chi_in, (Tc)1);
-    clover_apply<Tc, S>(acc, p, gv, s, V);
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[r][sp][k] = mk((Tc)0, (Tc)0);
+  if (MODE == DS_FULL || MODE == DS_BLOCK) clover_group<NR, Tin, Tc, S>(acc, ip, in_rs, nr, gv, s, V, chi);
+  hops_group_mu<0, MODE, NR, Tin, Tc, S>(acc, ip, in_rs, nr, gv, g, pos, mu_sel, chi);
+  asm volatile("" ::: "memory");
+  hops_group_mu<1, MODE, NR, Tin, Tc, S>(acc, ip, in_rs, nr, gv, g, pos, mu_sel, chi);
+  asm volatile("" ::: "memory");
+  hops_group_mu<2, MODE, NR, Tin, Tc, S>(acc, ip, in_rs, nr, gv, g, pos, mu_sel, chi);
+  asm volatile("" ::: "memory");
+  hops_group_mu<3, MODE, NR, Tin, Tc, S>(acc, ip, in_rs, nr, gv, g, pos, mu_sel, chi);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) break;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) op[(size_t)r * out_rs + (size_t)(3 * sp + k) * V + s] = cvt<Tout>(acc[r][sp][k]);
   }
-  hops_all<Tin, Tc, S, MODE>(acc, ip, gv, g, pos, mu_sel, chi_in);
-#pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) op[(size_t)(3 * sp + k) * V + s] = cvt<Tout>(acc[sp][k]);
+}
+
+template <typename Tin, typename Tout, typename S, typename Tc, int MODE, int NR>
+void launch_mode(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mu, int chi_in,
+                 size_t in_rs, size_t out_rs, size_t nsite, hipStream_t st) {
+  const unsigned grid = (unsigned)((nsite + TPB - 1) / TPB) * (unsigned)((nrhs + NR - 1) / NR);
+  dslash_kernel<Tin, Tout, S, Tc, MODE, NR><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rs, out_rs, nrhs);
+}
+
+// rhs per thread: 1 for a lone rhs; otherwise as many as the registers hold
+// without spilling (the accumulators of FP64 spinors are twice the size)
+template <typename Tin, typename Tout, typename S, typename Tc, int MODE>
+void launch_nr(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mu, int chi_in,
+               size_t in_rs, size_t out_rs, size_t nsite, hipStream_t st) {
+  if (nrhs == 1) {
+    launch_mode<Tin, Tout, S, Tc, MODE, 1>(out, in, gv, g, nrhs, mu, chi_in, in_rs, out_rs, nsite, st);
+  } else if constexpr (sizeof(Tc) == 8) {
+    launch_mode<Tin, Tout, S, Tc, MODE, 2>(out, in, gv, g, nrhs, mu, chi_in, in_rs, out_rs, nsite, st);
+  } else {
+    if (nrhs < 4)
+      launch_mode<Tin, Tout, S, Tc, MODE, 2>(out, in, gv, g, nrhs, mu, chi_in, in_rs, out_rs, nsite, st);
+    else
+      launch_mode<Tin, Tout, S, Tc, MODE, 4>(out, in, gv, g, nrhs, mu, chi_in, in_rs, out_rs, nsite, st);
+  }
 }
 
 }  // namespace
@@ -79,21 +236,18 @@ void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, con
   if (nrhs <= 0) return;
   const size_t nsite = (mode == DS_CROSS_FWD || mode == DS_CROSS_BWD) ? (size_t)g.nblocks * (g.vblock / g.bs[mu])
                                                                       : (size_t)g.V;
-  const unsigned grid = (unsigned)((nsite + TPB - 1) / TPB) * (unsigned)nrhs;
   switch (mode) {
     case DS_FULL:
-      dslash_kernel<Tin, Tout, S, Tc, DS_FULL><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride, nrhs);
+      launch_nr<Tin, Tout, S, Tc, DS_FULL>(out, in, gv, g, nrhs, mu, chi_in, in_rstride, out_rstride, nsite, st);
       break;
     case DS_BLOCK:
-      dslash_kernel<Tin, Tout, S, Tc, DS_BLOCK><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride, out_rstride, nrhs);
+      launch_nr<Tin, Tout, S, Tc, DS_BLOCK>(out, in, gv, g, nrhs, mu, chi_in, in_rstride, out_rstride, nsite, st);
       break;
     case DS_CROSS_FWD:
-      dslash_kernel<Tin, Tout, S, Tc, DS_CROSS_FWD><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride,
-                                                                          out_rstride, nrhs);
+      launch_nr<Tin, Tout, S, Tc, DS_CROSS_FWD>(out, in, gv, g, nrhs, mu, chi_in, in_rstride, out_rstride, nsite, st);
       break;
     default:
-      dslash_kernel<Tin, Tout, S, Tc, DS_CROSS_BWD><<<grid, TPB, 0, st>>>(out, in, gv, g, mu, chi_in, in_rstride,
-                                                                          out_rstride, nrhs);
+      launch_nr<Tin, Tout, S, Tc, DS_CROSS_BWD>(out, in, gv, g, nrhs, mu, chi_in, in_rstride, out_rstride, nsite, st);
       break;
   }
 }

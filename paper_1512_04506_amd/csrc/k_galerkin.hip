@@ -1,0 +1,203 @@
+// Block-crossing couplings of the coarse operator, Eq. (cgo):
+//
+//   (D_c)_{b, b+mu}[i][j] = w_i^{b dag} D_{b, b+mu} w_j^{b+mu}
+//     = -1/2 s sum_{x in F} < w_i(x), (1 - g_mu) U_mu(x) w_j(x + mu) >
+//
+// where F is the last layer of block b in direction mu (its sites are the
+// only ones with a forward neighbour in block b + mu) and s = -1 for the hop
+// across the time boundary.  With the forward spin projection
+// P_mu psi = psi_up - X_mu psi_dn (the 2-spinor a hop multiplies by the link)
+// and the reconstruction R u = (u, -X_mu^dag u), (1 - g_mu) v = R P_mu v and
+// <w, R u> = <P_mu w, u>, so each term is a 6-component inner product
+//
+//   < P_mu w_i(x), U_mu(x) P_mu w_j(x + mu) >.
+//
+// A basis vector lives on one chirality, so P_mu w is two of its spins
+// multiplied by phases +-1, +-i: exact copies of stored values.  Per block
+// and direction this is a complex contraction of 2 ntv rows by 2 ntv
+// columns over 6 |F| terms, which runs on the matrix cores (FP32
+// 32x32x2 MFMA, one wave per (row chirality, column chirality) tile).  Chunks
+// of GC_CS face sites are staged through LDS; the loads of the next chunk are
+// issued before the matrix products of the current one.
+#include "galerkin.h"
+
+namespace ddamg {
+
+namespace {
+
+typedef float gc_v16 __attribute__((ext_vector_type(16)));
+constexpr int GC_CS = 8;             // face sites per chunk
+constexpr int GC_ROWS = 6 * GC_CS;   // contraction terms per chunk
+constexpr int GC_LD = 33;            // padded row length (float2) in LDS
+constexpr int GC_NQ = 4;             // (spin, chirality, vector) entries per thread and chunk
+
+// P_mu w for w of chirality ch: component sg of the 2-spinor is
+// phase * w_spin.  ch = 0: (w_0, w_1).  ch = 1: -X_mu (w_2, w_3), i.e.
+// mu = 0: i (w_3, w_2); mu = 1: (w_3, -w_2); mu = 2: (i w_2, -i w_3);
+// mu = 3: (w_2, w_3).
+__device__ inline void proj_spin(int mu, int ch, int sg, int& spin, float& pr, float& pi) {
+  if (ch == 0) {
+    spin = sg;
+    pr = 1.f;
+    pi = 0.f;
+  } else if (mu == 0) {
+    spin = 3 - sg;
+    pr = 0.f;
+    pi = 1.f;
+  } else if (mu == 1) {
+    spin = 3 - sg;
+    pr = sg ? -1.f : 1.f;
+    pi = 0.f;
+  } else if (mu == 2) {
+    spin = 2 + sg;
+    pr = 0.f;
+    pi = sg ? -1.f : 1.f;
+  } else {
+    spin = 2 + sg;
+    pr = 1.f;
+    pi = 0.f;
+  }
+}
+
+__device__ inline int sel4(const int a[4], int mu) { return mu == 0 ? a[0] : mu == 1 ? a[1] : mu == 2 ? a[2] : a[3]; }
+
+template <typename S>
+__global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restrict__ Dc, BasisView<S> bv,
+                                                             GaugeView<float> gv, Geom g) {
+  __shared__ float2 Ps[2][GC_ROWS][GC_LD];  // [row chirality][term][row vector]
+  __shared__ float2 Qs[2][GC_ROWS][GC_LD];  // [column chirality][term][column vector]
+  // blocks in lexicographic order (through the XCD swizzle): the neighbour
+  // blocks read here are processed at about the same time on the same XCD
+  const int bl = xcd_swizzle(blockIdx.x, gridDim.x);
+  int bc[4];
+  bc[0] = bl % g.NB[0];
+  bc[1] = (bl / g.NB[0]) % g.NB[1];
+  bc[2] = (bl / (g.NB[0] * g.NB[1])) % g.NB[2];
+  bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
+  const int ci = block_to_int(g, bc);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int h = w >> 1, hp = w & 1;      // this wave's output tile
+  const int al = lane & 31, kk = lane >> 5;
+  const int xl = t % GC_CS, rest = t / GC_CS;  // staging: face site and entry
+  const int ntv = g.ntv, nc = g.nc;
+  const size_t V = g.V, nn = (size_t)nc * nc;
+
+  // raw values of one chunk: the basis at x (rows) and at x + mu (columns)
+  // for GC_NQ (spin, chirality, vector) entries, and the link at x
+  cx<float> praw[GC_NQ][3], qraw[GC_NQ][3], uraw[3][3];
+  float psc[GC_NQ], qsc[GC_NQ];
+  auto nsites_of = [&](int mu) { return g.vblock / sel4(g.bs, mu); };
+  auto fetch = [&](int mu, int f0) {
+    const int bsm = sel4(g.bs, mu);
+    int nb[4] = {bc[0], bc[1], bc[2], bc[3]};
+    for (int d = 0; d < 4; ++d)
+      if (d == mu) nb[d] = nb[d] + 1 == g.NB[d] ? 0 : nb[d] + 1;
+    const int cn = block_to_int(g, nb);
+    const int f = min(f0 + xl, nsites_of(mu) - 1);
+    const int lx = face_site(g, mu, bsm - 1, f);
+    const unsigned x = (unsigned)(ci * g.vblock + lx);
+    const unsigned y = (unsigned)(cn * g.vblock + lx - (bsm - 1) * sel4(g.lstr, mu));
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) uraw[a][b] = ldc<float>(gv.U + (size_t)(mu * 9 + 3 * a + b) * V, x);
+#pragma unroll
+    for (int q = 0; q < GC_NQ; ++q) {
+      const int r2 = rest + 32 * q;
+      const int sg = r2 & 1, ch = (r2 >> 1) & 1, av = min(r2 >> 2, ntv - 1);
+      int spin;
+      float pr, pi;
+      proj_spin(mu, ch, sg, spin, pr, pi);
+      const stc_t<S>* wb = bv.W + (size_t)(av * 12 + 3 * spin) * V;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        praw[q][c] = ldc<float>(wb + (size_t)c * V, x);
+        qraw[q][c] = ldc<float>(wb + (size_t)c * V, y);
+      }
+      if constexpr (is_half<S>()) {
+        psc[q] = bv.Wsc[(size_t)av * V + x];
+        qsc[q] = bv.Wsc[(size_t)av * V + y];
+      } else {
+        psc[q] = qsc[q] = 1.f;
+      }
+    }
+  };
+  auto store = [&](int mu, int f0) {
+    const bool fin = f0 + xl < nsites_of(mu);
+#pragma unroll
+    for (int q = 0; q < GC_NQ; ++q) {
+      const int r2 = rest + 32 * q;
+      const int sg = r2 & 1, ch = (r2 >> 1) & 1, av = r2 >> 2;
+      int spin;
+      float pr, pi;
+      proj_spin(mu, ch, sg, spin, pr, pi);
+      const bool ok = fin && av < ntv;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<float> pv = psc[q] * praw[q][c];
+        cx<float> u = mk(0.f, 0.f);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) u = cfma(uraw[c][b], qraw[q][b], u);
+        u = qsc[q] * u;
+        const int row = xl * 6 + sg * 3 + c;
+        Ps[ch][row][av] = ok ? make_float2(pr * pv.r - pi * pv.i, pr * pv.i + pi * pv.r) : make_float2(0.f, 0.f);
+        Qs[ch][row][av] = ok ? make_float2(pr * u.r - pi * u.i, pr * u.i + pi * u.r) : make_float2(0.f, 0.f);
+      }
+    }
+  };
+
+  gc_v16 RR, II, RI, IR;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) RR[v] = II[v] = RI[v] = IR[v] = 0.f;
+  int mu = 0, f0 = 0;
+  fetch(0, 0);
+  for (;;) {
+    __syncthreads();  // the previous chunk has been consumed
+    store(mu, f0);
+    int nmu = mu, nf0 = f0 + GC_CS;
+    if (nf0 >= nsites_of(mu)) {
+      nmu = mu + 1;
+      nf0 = 0;
+    }
+    if (nmu < 4) fetch(nmu, nf0);
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < GC_ROWS / 2; ++tt) {
+      const float2 pv = Ps[h][2 * tt + kk][al];
+      const float2 qv = Qs[hp][2 * tt + kk][al];
+      RR = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.x, qv.x, RR, 0, 0, 0);
+      II = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.y, qv.y, II, 0, 0, 0);
+      RI = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.x, qv.y, RI, 0, 0, 0);
+      IR = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.y, qv.x, IR, 0, 0, 0);
+    }
+    if (nmu != mu) {
+      // slot 1 + 2 mu done: sum conj(p) q = (RR + II, RI - IR)
+      const float coef = (mu == 3 && bc[3] == g.NB[3] - 1) ? 0.5f : -0.5f;
+      cx<float>* out = Dc + ((size_t)ci * 9 + 1 + 2 * mu) * nn + (size_t)(hp * ntv + al) * nc + h * ntv;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ai = 8 * (v / 4) + 4 * kk + (v % 4);
+        if (ai < ntv && al < ntv) out[ai] = mk(coef * (RR[v] + II[v]), coef * (RI[v] - IR[v]));
+        RR[v] = II[v] = RI[v] = IR[v] = 0.f;
+      }
+      if (nmu == 4) break;
+    }
+    mu = nmu;
+    f0 = nf0;
+  }
+}
+
+}  // namespace
+
+template <typename S>
+void launch_galerkin_cross(cx<float>* Dc, const BasisView<S>& bv, const GaugeView<float>& gv, const Geom& g,
+                           hipStream_t st) {
+  galerkin_cross_kernel<S><<<g.nblocks, 256, 0, st>>>(Dc, bv, gv, g);
+}
+
+template void launch_galerkin_cross<float>(cx<float>*, const BasisView<float>&, const GaugeView<float>&, const Geom&,
+                                           hipStream_t);
+template void launch_galerkin_cross<__half>(cx<float>*, const BasisView<__half>&, const GaugeView<float>&,
+                                            const Geom&, hipStream_t);
+
+}  // namespace ddamg

@@ -62,17 +62,20 @@ def make_ctx(dd, L, block, eps, m0, ntv, prec, seed=7, **kw):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_dirac_apply(case, prec):
+@pytest.mark.parametrize("nrhs", [1, 3, 6])
+def test_dirac_apply(case, prec, nrhs):
+    # 1, 3 and 6 rhs: a lone rhs, and groups of 2 or 4 rhs per thread with a
+    # ragged last group
     dd = _gpu()
     L, block, eps, m0, ntv = CASES[case]
-    say("dirac_apply", case, "prec", prec)
-    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    say("dirac_apply", case, "prec", prec, "nrhs", nrhs)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, max_rhs=6)
     A = dirac.clover_term(U, m0, 1.0)
-    psi = synth.gaussian_spinors(L, 3, 11)
+    psi = synth.gaussian_spinors(L, nrhs, 11)
     out = torch.zeros_like(dev(psi))
-    ctx.dirac_apply(out, dev(psi), 3, prec)
+    ctx.dirac_apply(out, dev(psi), nrhs, prec)
     got = host(out)
-    ref = np.stack([dirac.apply_D(U, A, psi[r]) for r in range(3)])
+    ref = np.stack([dirac.apply_D(U, A, psi[r]) for r in range(nrhs)])
     assert rel(got, ref) <= TOL[prec]
 
 

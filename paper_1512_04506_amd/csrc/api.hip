@@ -685,7 +685,8 @@ struct Solver final : SolverBase {
   // h1 = V^H w; w <- w - V h1 and h2 = V^H w in one fused pass; the norm of
   // w'' = w - V h2 from |w|^2 - |h2|^2 (V orthonormal); w <- w'' / |w''| in
   // one pass.  The Arnoldi column is h1 + h2 with subdiagonal |w''|.
-  void cgs2(cx<double>* V, size_t vsj, int k, int nrhs) {
+  // w32: FP32 copy of the new basis vector (the next V-cycle's input), if given
+  void cgs2(cx<double>* V, size_t vsj, int k, int nrhs, cx<float>* w32) {
     const size_t n = fsz();
     const int* act = ok.active.get<int>();
     cx<double>* w = V + (size_t)(k + 1) * vsj;
@@ -702,7 +703,7 @@ struct Solver final : SolverBase {
     launch_gs_norm(ok.n2.get<cx<double>>(), ok.wscale.get<double>(), ok.h2.get<cx<double>>(), ok.ldh, k + 1, nrhs,
                    act, st);
     launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h2.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st,
-                                 ok.wscale.get<double>());
+                                 ok.wscale.get<double>(), w32);
   }
 
   // The outer basis V (FP64) and the preconditioned vectors Z grow with the
@@ -801,7 +802,12 @@ struct Solver final : SolverBase {
       }
       if (its >= c->p.outer_maxit) break;
       launch_arnoldi_start(ok.st, ok.n2.get<cx<double>>(), 1, nrhs, st);
-      launch_scale<double, double>(V, n, V, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st);
+      // V-cycle input: in FP32 a copy written with each new basis vector, in
+      // FP64 the basis vector itself
+      constexpr bool f32 = std::is_same<T, float>::value;
+      cx<float>* v32 = nullptr;
+      if constexpr (f32) v32 = fy.get<cx<float>>();
+      launch_scale<double, double>(V, n, V, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st, v32);
       int k = 0;
       for (; k < m && its < c->p.outer_maxit; ++k) {
         grow_outer(k + 2);
@@ -810,8 +816,10 @@ struct Solver final : SolverBase {
         cx<double>* vk = V + (size_t)k * vsj;
         cx<T>* zk = Z + (size_t)k * vsj;
         // z_k = M^{-1} v_k
-        launch_copy<T, double>(fy.get<cx<T>>(), n, vk, n, n, nrhs, st);
-        vcycle(zk, fy.get<cx<T>>(), nrhs);
+        if constexpr (f32)
+          vcycle(zk, fy.get<cx<T>>(), nrhs);
+        else
+          vcycle(zk, vk, nrhs);
         // w = D z_k (FP64 operator)
         cx<double>* wk = V + (size_t)(k + 1) * vsj;
         c->timed(DDAMG_KERNEL_DSLASH, nrhs, [&] {
@@ -820,7 +828,7 @@ struct Solver final : SolverBase {
           else
             launch_dslash<float, double, double, double>(wk, zk, g64, g, nrhs, DS_FULL, 0, -1, n, n, st);
         });
-        c->timed(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { cgs2(V, vsj, k, nrhs); });
+        c->timed(DDAMG_KERNEL_OUTER_GS, nrhs, [&] { cgs2(V, vsj, k, nrhs, v32); });
         launch_arnoldi_column(ok.st, k, ok.h1.get<cx<double>>(), ok.h2.get<cx<double>>(), ok.ldh,
                               ok.n2.get<cx<double>>(), 1, nrhs, st);
         ++its;

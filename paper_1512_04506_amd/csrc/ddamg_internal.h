@@ -323,11 +323,12 @@ int blas_nchunks(size_t n);
 template <typename T>
 void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size_t vstride_j, size_t vstride_r,
                  int nvec, const cx<T>* w, size_t wstride_r, size_t n, int nrhs, const int* active, hipStream_t st);
-// w[r] += sign * sum_j h[r * ldh + j] * V_j[r]
+// w[r] += sign * sum_j h[r * ldh + j] * V_j[r], then w[r] *= post[r] if post;
+// w32 (same strides) receives an FP32 copy of the result if given
 template <typename Tw, typename Tv>
 void launch_maxpy(cx<Tw>* w, size_t wstride_r, const cx<Tv>* Vb, size_t vstride_j, size_t vstride_r, int nvec,
                   const cx<double>* h, int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st,
-                  const double* post = nullptr);
+                  const double* post = nullptr, cx<float>* w32 = nullptr);
 // Fused second Gram-Schmidt pass over FP64 vectors: w <- w - V h1, then
 // h2[r][j] = V_j^H w (j < nvec) and h2[r][nvec] = |w|^2, nvec <= GS_FUSED_MAXV
 constexpr int GS_FUSED_MAXV = 24;
@@ -337,10 +338,11 @@ void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>
 // n2[r] = h2[r][nvec] - sum_{j<nvec} |h2[r][j]|^2, inv[r] = 1/sqrt(n2[r]) (0 if not positive)
 void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs,
                     const int* active, hipStream_t st);
-// y[r] = s[r] * x[r] (s real double, per rhs) ; y and x may alias
+// y[r] = s[r] * x[r] (s real double, per rhs) ; y and x may alias; y32 (same
+// strides as y) receives an FP32 copy of y if given
 template <typename Ty, typename Tx>
 void launch_scale(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, const double* s, size_t n, int nrhs,
-                  const int* active, hipStream_t st);
+                  const int* active, hipStream_t st, cx<float>* y32 = nullptr);
 // abstol[r] = tol * |n2[r]|^(1/2) (tol < 0 gives -1); s[r] = |n2[r]|^(-1/2)
 // with *status set to 1 if a norm is zero or not finite (nrhs <= 64)
 void launch_set_abstol(double* abstol, const cx<double>* n2, double tol, int nrhs, hipStream_t st);

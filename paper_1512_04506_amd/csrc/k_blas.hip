@@ -75,11 +75,13 @@ __global__ void mdot_final_kernel(cx<double>* h, int ldh, const cx<double>* part
   if (threadIdx.x == 0) h[(size_t)r * ldh + j] = mk(re, im);
 }
 
-// w <- (w + sign sum_j h_j V_j) [* post[r] if post]
+// w <- (w + sign sum_j h_j V_j) [* post[r] if post], and an FP32 copy of the
+// result in w32 (same strides) if w32 is given
 template <typename Tw, typename Tv>
 __global__ __launch_bounds__(BT) void maxpy_kernel(cx<Tw>* w, size_t wsr, const cx<Tv>* __restrict__ Vb, size_t vsj,
                                                    size_t vsr, int nvec, const cx<double>* __restrict__ h, int ldh,
-                                                   double sign, size_t n, const int* active, const double* post) {
+                                                   double sign, size_t n, const int* active, const double* post,
+                                                   cx<float>* w32) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   using Tc = typename std::conditional<(sizeof(Tw) > sizeof(Tv)), Tw, Tv>::type;
@@ -89,7 +91,9 @@ __global__ __launch_bounds__(BT) void maxpy_kernel(cx<Tw>* w, size_t wsr, const 
     cx<Tc> acc = cvt<Tc>(w[(size_t)r * wsr + i]);
     for (int j = 0; j < nvec; ++j)
       acc = acc + cvt<Tc>(sign * hr[j]) * cvt<Tc>(Vb[(size_t)j * vsj + (size_t)r * vsr + i]);
-    w[(size_t)r * wsr + i] = cvt<Tw>(f * acc);
+    const cx<Tw> res = cvt<Tw>(f * acc);
+    w[(size_t)r * wsr + i] = res;
+    if (w32) w32[(size_t)r * wsr + i] = cvt<float>(res);
   }
 }
 
@@ -167,13 +171,15 @@ __global__ void gs_norm_kernel(cx<double>* n2, double* inv, const cx<double>* h2
 
 template <typename Ty, typename Tx>
 __global__ __launch_bounds__(BT) void scale_kernel(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr,
-                                                   const double* s, size_t n, const int* active) {
+                                                   const double* s, size_t n, const int* active, cx<float>* y32) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   const double f = s[r];
   for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < n; i += (size_t)gridDim.x * BT) {
     cx<double> v = cvt<double>(x[(size_t)r * xstr + i]);
-    y[(size_t)r * ystr + i] = cvt<Ty>(f * v);
+    const cx<Ty> res = cvt<Ty>(f * v);
+    y[(size_t)r * ystr + i] = res;
+    if (y32) y32[(size_t)r * ystr + i] = cvt<float>(res);
   }
 }
 
@@ -352,10 +358,11 @@ void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size
 
 template <typename Tw, typename Tv>
 void launch_maxpy(cx<Tw>* w, size_t wsr, const cx<Tv>* Vb, size_t vsj, size_t vsr, int nvec, const cx<double>* h,
-                  int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st, const double* post) {
-  if (nrhs <= 0 || (nvec <= 0 && !post)) return;
+                  int ldh, double sign, size_t n, int nrhs, const int* active, hipStream_t st, const double* post,
+                  cx<float>* w32) {
+  if (nrhs <= 0 || (nvec <= 0 && !post && !w32)) return;
   maxpy_kernel<Tw, Tv>
-      <<<dim3(grid_for(n), nrhs), BT, 0, st>>>(w, wsr, Vb, vsj, vsr, nvec, h, ldh, sign, n, active, post);
+      <<<dim3(grid_for(n), nrhs), BT, 0, st>>>(w, wsr, Vb, vsj, vsr, nvec, h, ldh, sign, n, active, post, w32);
 }
 
 void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>* Vb, size_t vsj, size_t vsr,
@@ -376,9 +383,9 @@ void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, 
 
 template <typename Ty, typename Tx>
 void launch_scale(cx<Ty>* y, size_t ystr, const cx<Tx>* x, size_t xstr, const double* s, size_t n, int nrhs,
-                  const int* active, hipStream_t st) {
+                  const int* active, hipStream_t st, cx<float>* y32) {
   if (nrhs <= 0) return;
-  scale_kernel<Ty, Tx><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(y, ystr, x, xstr, s, n, active);
+  scale_kernel<Ty, Tx><<<dim3(grid_for(n), nrhs), BT, 0, st>>>(y, ystr, x, xstr, s, n, active, y32);
 }
 
 template <typename T>
@@ -411,9 +418,9 @@ template void launch_mdot<float>(cx<double>*, int, cx<double>*, const cx<float>*
                                  const cx<float>*, size_t, size_t, int, const int*, hipStream_t);
 #define INST2(A, B)                                                                                                   \
   template void launch_maxpy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, const cx<double>*, int, double, \
-                                   size_t, int, const int*, hipStream_t, const double*);                              \
+                                   size_t, int, const int*, hipStream_t, const double*, cx<float>*);                  \
   template void launch_scale<A, B>(cx<A>*, size_t, const cx<B>*, size_t, const double*, size_t, int, const int*,      \
-                                   hipStream_t);                                                                      \
+                                   hipStream_t, cx<float>*);                                                          \
   template void launch_copy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, hipStream_t);
 INST2(double, double)
 INST2(float, float)

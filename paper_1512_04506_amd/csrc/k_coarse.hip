@@ -402,6 +402,72 @@ __global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__
   }
 }
 
+// The same stencil (without Dmat) for many rhs in FP32 on the matrix cores:
+// 16x16x4 MFMA with a tile of 16 rows of D_c per wave, up to 16 rhs as the
+// columns and the components of the neighbour as K.  The A operand (16
+// consecutive rows of one column of a column-major slot block) and the B
+// operand (4 components of 16 rhs of the neighbour vector, an L2-resident
+// read) come straight from memory; the slot's factor (and FP16 scale) is
+// applied to B.  At 12 rhs the FP32 multiply-adds per byte of D_c are above
+// what the vector ALUs sustain at HBM rate; on the matrix cores the stencil
+// streams D_c.  The workgroup is one coarse site and 16 rhs, one wave per
+// row tile.
+typedef float cm_v4 __attribute__((ext_vector_type(4)));
+constexpr int CM_RHS = 16;
+
+template <typename S>
+__global__ __launch_bounds__(256) void coarse_mfma_kernel(cx<float>* __restrict__ out, size_t ostr, int out_first,
+                                                          const cx<float>* __restrict__ add, size_t astr,
+                                                          const cx<float>* __restrict__ xs, size_t xsstr,
+                                                          int xs_first, float cs, const cx<float>* __restrict__ xn,
+                                                          size_t xnstr, int xn_first, float cn, CoarseView<S> cv,
+                                                          int nc, int nrhs) {
+  const int ci = out_first + blockIdx.x;
+  const int r0 = blockIdx.y * CM_RHS;
+  const int nr = min(CM_RHS, nrhs - r0);
+  const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int arow = min(rt * 16 + li, nc - 1);  // A: row li of the tile (clamped)
+  const int bj = min(li, nr - 1);               // B: rhs li (clamped)
+  const size_t nn = (size_t)nc * nc;
+  cm_v4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+  const int s_beg = cs != 0.f ? 0 : 1;
+  const int s_end = cn != 0.f ? 9 : 1;
+  for (int slot = s_beg; slot < s_end; ++slot) {
+    const int nb = slot == 0 ? ci : cv.nbr[ci * 9 + slot];
+    const cx<float>* xv = slot == 0 ? xs + (size_t)(nb - xs_first) * nc + (size_t)(r0 + bj) * xsstr
+                                    : xn + (size_t)(nb - xn_first) * nc + (size_t)(r0 + bj) * xnstr;
+    float coef = slot == 0 ? cs : cn;
+    if constexpr (is_half<S>()) coef *= cv.Dsc[ci * 9 + slot];
+    const stc_t<S>* Dp = cv.D + ((size_t)ci * 9 + slot) * nn + arow;
+#pragma unroll 4
+    for (int k0 = 0; k0 < nc; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kin = k < nc;
+      const int kc = kin ? k : nc - 1;
+      const cx<float> a = ldc<float>(Dp, (size_t)kc * nc);
+      const cx<float> xb = xv[kc];
+      const float br = kin ? coef * xb.r : 0.f, bi = kin ? coef * xb.i : 0.f;
+      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r, br, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.i, bi, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r, bi, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.i, br, acci, 0, 0, 0);
+    }
+  }
+  // lane: rows 4 lk + v of the tile, rhs li
+  if (li < nr) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rt * 16 + 4 * lk + v;
+      if (row < nc) {
+        cx<float> o = mk(accr[v], acci[v]);
+        if (add) o = o + add[(size_t)(r0 + li) * astr + (size_t)(ci - out_first) * nc + row];
+        out[(size_t)(r0 + li) * ostr + (size_t)(ci - out_first) * nc + row] = o;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ Eq. (dagger) fill
 // backward block of the neighbour j = i + mu:
 //   D[j][2+2mu](row, col) = s_row s_col conj(D[i][1+2mu](col, row)),
@@ -655,6 +721,15 @@ void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T
     coarse_stencil_kernel<T, S, 4, 2><<<dim3(nout, 1), CG * (nc / 2), (size_t)CG * nc * 4 * sizeof(cx<T>), st>>>(
         out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
   } else {
+    if constexpr (std::is_same<T, float>::value) {
+      // many rhs in FP32: matrix cores (a wave per 16-row tile, at most 4)
+      if (!Dmat && nc <= 64) {
+        const int tiles = (nc + 15) / 16;
+        coarse_mfma_kernel<S><<<dim3(nout, (nrhs + CM_RHS - 1) / CM_RHS), 64 * tiles, 0, st>>>(
+            out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, nc, nrhs);
+        return;
+      }
+    }
     const int CG = cg_for(12, 1);
     coarse_stencil_kernel<T, S, 12, 1><<<dim3(nout, (nrhs + 11) / 12), CG * nc, (size_t)CG * nc * 12 * sizeof(cx<T>), st>>>(
         out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);

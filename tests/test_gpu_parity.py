@@ -137,6 +137,13 @@ def test_coarse_operator_restrict_prolong(case, prec):
     nbr = coarse.neighbour_table(blk)
     ref = coarse.coarse_apply(Dc_ref, nbr, xc.reshape(2, nb, n)).reshape(xc.shape)
     assert rel(host(out), ref) <= TOL[prec]
+    # seventeen rhs: the matrix-core stencil (FP32 paths), a full and a
+    # one-rhs tile
+    xc17 = synth.gaussian_coarse(nb, ntv, 17, 34)
+    out17 = torch.zeros_like(dev(xc17))
+    ctx.coarse_apply(out17, dev(xc17), 17)
+    ref17 = coarse.coarse_apply(Dc_ref, nbr, xc17.reshape(17, nb, n)).reshape(xc17.shape)
+    assert rel(host(out17), ref17) <= TOL[prec]
 
 
 @pytest.mark.parametrize("geom", [((4, 4, 4, 4), (2, 2, 2, 2), 20), ((8, 4, 4, 4), (4, 2, 2, 2), 16)])
@@ -150,7 +157,7 @@ def test_coarse_operator_many_test_vectors(prec, geom):
     L, block, ntv = geom
     eps, m0 = 0.3, -0.1
     say("coarse operator", L, block, "ntv", ntv, "prec", prec)
-    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, max_rhs=6)
     A = dirac.clover_term(U, m0, 1.0)
     blk, W = _basis(L, block, ntv)
     ctx.import_basis(dev(W))
@@ -159,6 +166,12 @@ def test_coarse_operator_many_test_vectors(prec, geom):
     Dc = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
     ctx.export_coarse(Dc)
     assert rel(host(Dc), Dc_ref) <= TOL[prec]
+    # six rhs through the stencil (row tiles of 16 over 2 ntv = 40 or 32 rows)
+    xc = synth.gaussian_coarse(nb, ntv, 6, 35)
+    out = torch.zeros_like(dev(xc))
+    ctx.coarse_apply(out, dev(xc), 6)
+    ref = coarse.coarse_apply(Dc_ref, coarse.neighbour_table(blk), xc.reshape(6, nb, n)).reshape(xc.shape)
+    assert rel(host(out), ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("case", ["c1_4x4x4x4", "ragged_6x4x4x4"])

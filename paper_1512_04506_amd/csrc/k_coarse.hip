@@ -37,7 +37,6 @@ struct RTile {
   static constexpr int AT = sizeof(T) == 8 ? 1 : 2;
   static constexpr int NV = AT * 2 * RT * 2;
 };
-constexpr int RT = 4;  // rhs tile of the prolongation
 
 // One halving step of the butterfly, unrolled at compile time so that every
 // register index is static: lanes with bit HALF set keep the upper half of
@@ -265,50 +264,63 @@ __global__ __launch_bounds__(256) void restrict_mfma_kernel(cx<float>* __restric
 }
 
 // ---------------------------------------------------------- prolongation
-// One workgroup per block, one lane per site; the block's coarse vector of
-// every rhs sits in LDS and is read as a broadcast.
+// x[r](site, k) = sum_a W_a(site, k) x_c[r](block, h(k), a).  Workgroup =
+// (block, group of KP spin-colour components of one chirality h), the group
+// fastest so that the workgroups of a block (which share its scales) run
+// side by side on one XCD; one lane per site.  Each basis entry is loaded
+// once per pass of PT rhs and feeds them all; the block's coarse vectors of
+// chirality h sit in LDS and each broadcast read feeds the KP components
+// (three in FP32; one in FP64, for the register file).
+constexpr int PT = 12;  // rhs per pass of the prolongation
+template <typename T>
+constexpr int prolong_kp() { return sizeof(T) == 8 ? 1 : 3; }
+
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void prolong_kernel(cx<T>* __restrict__ x, size_t xstr, const cx<T>* __restrict__ xc,
                                                       size_t cstr, BasisView<S> bv, Geom g, int nrhs) {
+  constexpr int KP = prolong_kp<T>(), NG = 12 / KP;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-  cx<T>* xl = reinterpret_cast<cx<T>*>(smem_raw);  // [nrhs][nc]
-  const int ci = blockIdx.x;
+  cx<T>* xl = reinterpret_cast<cx<T>*>(smem_raw);  // [nrhs][ntv] of chirality h
+  const int wl = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int ci = wl / NG, k0 = (wl % NG) * KP, h = k0 / 6;
   const int l = threadIdx.x;
+  const int ntv = g.ntv;
   const size_t V = g.V;
-  for (int e = l; e < nrhs * g.nc; e += blockDim.x) {
-    const int r = e / g.nc, k = e % g.nc;
-    xl[e] = xc[(size_t)r * cstr + (size_t)ci * g.nc + k];
+  for (int e = l; e < nrhs * ntv; e += blockDim.x) {
+    const int r = e / ntv, a = e % ntv;
+    xl[e] = xc[(size_t)r * cstr + (size_t)ci * g.nc + h * ntv + a];
   }
   __syncthreads();
   if (l >= g.vblock) return;
-  const size_t site = (size_t)ci * g.vblock + l;
-  for (int r0 = 0; r0 < nrhs; r0 += RT) {
-    const int nr = min(RT, nrhs - r0);
-    cx<T> acc[RT][12];
+  const unsigned site = (unsigned)(ci * g.vblock + l);
+  for (int r0 = 0; r0 < nrhs; r0 += PT) {
+    const int nr = min(PT, nrhs - r0);
+    cx<T> acc[PT][KP];
 #pragma unroll
-    for (int j = 0; j < RT; ++j)
+    for (int j = 0; j < PT; ++j)
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[j][k] = mk((T)0, (T)0);
-    for (int a = 0; a < g.ntv; ++a) {
+      for (int q = 0; q < KP; ++q) acc[j][q] = mk((T)0, (T)0);
+#pragma unroll 2
+    for (int a = 0; a < ntv; ++a) {
       T sc = (T)1;
-      if constexpr (is_half<S>()) sc = (T)bv.Wsc[(size_t)a * V + site];
-      cx<T> wv[12];
+      if constexpr (is_half<S>()) sc = (T)elem(bv.Wsc + (size_t)a * V, site);
+      cx<T> wv[KP];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) wv[k] = sc * ldc<T>(bv.W, ((size_t)a * 12 + k) * V + site);
+      for (int q = 0; q < KP; ++q) wv[q] = sc * ldc<T>(bv.W + ((size_t)a * 12 + k0 + q) * V, site);
 #pragma unroll
-      for (int j = 0; j < RT; ++j) {
-        if (j >= nr) break;
-        const cx<T> cl = xl[(r0 + j) * g.nc + a], cr = xl[(r0 + j) * g.nc + g.ntv + a];
+      for (int j = 0; j < PT; ++j) {
+        if (j < nr) {
+          const cx<T> c = xl[(r0 + j) * ntv + a];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[j][k] = acc[j][k] + wv[k] * (k < 6 ? cl : cr);
+          for (int q = 0; q < KP; ++q) acc[j][q] = acc[j][q] + wv[q] * c;
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < RT; ++j) {
-      if (j >= nr) break;
+    for (int j = 0; j < PT; ++j)
+      if (j < nr)
 #pragma unroll
-      for (int k = 0; k < 12; ++k) x[(size_t)(r0 + j) * xstr + (size_t)k * V + site] = acc[j][k];
-    }
+        for (int q = 0; q < KP; ++q) x[(size_t)(r0 + j) * xstr + (size_t)(k0 + q) * V + site] = acc[j][q];
   }
 }
 
@@ -695,8 +707,8 @@ void launch_prolong(cx<T>* x, size_t xstr, const cx<T>* xc, size_t cstr, const B
                     int nrhs, hipStream_t st) {
   if (nrhs <= 0) return;
   const int threads = ((g.vblock + 63) / 64) * 64;
-  const size_t lds = (size_t)nrhs * g.nc * sizeof(cx<T>);
-  prolong_kernel<T, S><<<g.nblocks, threads, lds, st>>>(x, xstr, xc, cstr, bv, g, nrhs);
+  const size_t lds = (size_t)nrhs * g.ntv * sizeof(cx<T>);
+  prolong_kernel<T, S><<<g.nblocks * (12 / prolong_kp<T>()), threads, lds, st>>>(x, xstr, xc, cstr, bv, g, nrhs);
 }
 
 namespace {

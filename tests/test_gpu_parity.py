@@ -131,6 +131,11 @@ def test_coarse_operator_restrict_prolong(case, prec):
     x = torch.zeros_like(dev(y))
     ctx.mg_prolong(x, dev(xc), 2)
     assert rel(host(x), coarse.prolong(blk, W, xc)) <= TOL[prec]
+    # seventeen rhs: a full pass of twelve and a ragged one
+    xp17 = synth.gaussian_coarse(nb, ntv, 17, 36)
+    x17 = torch.zeros_like(dev(y9))
+    ctx.mg_prolong(x17, dev(xp17), 17)
+    assert rel(host(x17), coarse.prolong(blk, W, xp17)) <= TOL[prec]
     # stencil apply
     out = torch.zeros_like(dev(xc))
     ctx.coarse_apply(out, dev(xc), 2)

@@ -525,11 +525,10 @@ struct Solver final : SolverBase {
     }
     const int CH = std::min(g.ntv, (int)GAL_CHUNK);
     cx<T>* Zp = ws_Z.get<cx<T>>();
-    // FP32 assembly with up to 32 test vectors: the block-crossing pieces
-    // come from one fused contraction of the basis (no D P field); otherwise
-    // every piece is D applied to the basis, then restricted
-    constexpr bool f32 = std::is_same<T, float>::value;
-    const bool fused_cross = f32 && g.ntv <= GALERKIN_CROSS_MAX_NTV;
+    // with up to 32 test vectors the block-crossing pieces come from one
+    // fused contraction of the basis (no D P field); otherwise every piece
+    // is D applied to the basis, then restricted
+    const bool fused_cross = g.ntv <= GALERKIN_CROSS_MAX_NTV;
     const int npiece = fused_cross ? 1 : 5;
     for (int hp = 0; hp < 2; ++hp)
       for (int a0 = 0; a0 < g.ntv; a0 += CH) {
@@ -547,10 +546,8 @@ struct Solver final : SolverBase {
           });
         }
       }
-    if constexpr (f32) {
-      if (fused_cross)
-        c->timed(DDAMG_KERNEL_SETUP_GALERKIN, 2 * g.ntv, [&] { launch_galerkin_cross<S>(D, bv(), gva, g, st); });
-    }
+    if (fused_cross)
+      c->timed(DDAMG_KERNEL_SETUP_GALERKIN, 2 * g.ntv, [&] { launch_galerkin_cross<T, S>(D, bv(), gva, g, st); });
     launch_dagger_fill<T>(D, c->nbr.get<int>(), g, st);
     launch_quantize_coarse<T, S>(Dq.get<stc_t<S>>(), Dsc.get<float>(), D, g, st);
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));

@@ -10,10 +10,10 @@ namespace ddamg {
 constexpr int GALERKIN_CROSS_MAX_NTV = 32;
 
 // Writes the forward slots 1 + 2 mu (mu = 0..3) of every coarse site of
-// Dc [Nb][9][col][row] (FP32) from the stored basis bv and the FP32 links.
-// Requires g.ntv <= GALERKIN_CROSS_MAX_NTV; other slots are left alone.
-template <typename S>
-void launch_galerkin_cross(cx<float>* Dc, const BasisView<S>& bv, const GaugeView<float>& gv, const Geom& g,
-                           hipStream_t st);
+// Dc [Nb][9][col][row] (precision T, FP32 or FP64) from the stored basis bv
+// and the links in T.  Requires g.ntv <= GALERKIN_CROSS_MAX_NTV; other slots
+// are left alone.
+template <typename T, typename S>
+void launch_galerkin_cross(cx<T>* Dc, const BasisView<S>& bv, const GaugeView<T>& gv, const Geom& g, hipStream_t st);
 
 }  // namespace ddamg

@@ -263,6 +263,93 @@ __global__ __launch_bounds__(256) void restrict_mfma_kernel(cx<float>* __restric
   }
 }
 
+// The FP64 restriction of many rhs on the FP64 matrix cores (16x16x4
+// MFMA).  Workgroup = (block, 32 rhs); wave = (chirality h, tile of 16 test
+// vectors), each over both 16-rhs tiles and every staged chunk, so no
+// partial sums cross waves.  Chunks of RD_CS sites (rows: site x component
+// of chirality h) are staged in LDS as in the FP32 kernel, the next chunk's
+// loads in flight during the products.
+typedef double rd_v4 __attribute__((ext_vector_type(4)));
+constexpr int RD_CS = 4;
+constexpr int RD_ROWS = RD_CS * 6;
+constexpr int RESTRICT_MFMA64_MIN_RHS = 4;
+
+__global__ __launch_bounds__(256) void restrict_mfma64_kernel(cx<double>* __restrict__ out, size_t ostr_r,
+                                                              size_t ostr_b, const cx<double>* __restrict__ y,
+                                                              size_t ystr, BasisView<double> bv, Geom g, int nrhs,
+                                                              int face_mu) {
+  __shared__ cx<double> Ws[2][RD_ROWS][RM_LD];  // [h][row][a]
+  __shared__ cx<double> Ys[2][RD_ROWS][RM_LD];  // [h][row][rhs]
+  const int ci = blockIdx.x;
+  const int col0 = blockIdx.y * 32;
+  const int l = threadIdx.x, lane = l & 63, w = l >> 6;
+  const int h = w >> 1, ti = w & 1;
+  const int ntv = g.ntv;
+  const int ncol = min(32, nrhs - col0);
+  const size_t V = g.V;
+  const size_t base = (size_t)ci * g.vblock;
+  const int nsites = face_mu < 0 ? g.vblock : g.vblock / g.bs[face_mu];
+  rd_v4 RR[2], II[2], RI[2], IR[2];
+#pragma unroll
+  for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) RR[tj][v] = II[tj][v] = RI[tj][v] = IR[tj][v] = 0.0;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int nW = 12 * ntv * RD_CS, nY = 12 * ncol * RD_CS;
+  constexpr int NQ = (12 * 32 * RD_CS + 255) / 256;
+  cx<double> wraw[NQ], yraw[NQ];
+  auto fetch = [&](int f0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = l + 256 * q;
+      const int xl = e % RD_CS, rest = e / RD_CS, comp = rest % 12, idx = rest / 12;
+      const int f = min(f0 + xl, nsites - 1);
+      const size_t x = base + (face_mu < 0 ? f : face_site(g, face_mu, g.bs[face_mu] - 1, f));
+      const int ia = min(idx, ntv - 1), ir = min(idx, ncol - 1);
+      wraw[q] = bv.W[((size_t)ia * 12 + comp) * V + x];
+      yraw[q] = y[(size_t)(col0 + ir) * ystr + (size_t)comp * V + x];
+    }
+  };
+  fetch(0);
+  for (int f0 = 0; f0 < nsites; f0 += RD_CS) {
+    __syncthreads();  // previous chunk consumed
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = l + 256 * q;
+      const int xl = e % RD_CS, rest = e / RD_CS, comp = rest % 12, idx = rest / 12;
+      const bool fin = f0 + xl < nsites;
+      if (idx < 32) {
+        Ws[comp / 6][xl * 6 + comp % 6][idx] = (fin && e < nW) ? wraw[q] : mk(0.0, 0.0);
+        Ys[comp / 6][xl * 6 + comp % 6][idx] = (fin && e < nY) ? yraw[q] : mk(0.0, 0.0);
+      }
+    }
+    if (f0 + RD_CS < nsites) fetch(f0 + RD_CS);
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < RD_ROWS; k0 += 4) {
+      const cx<double> wv = Ws[h][k0 + k4][16 * ti + i16];
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        const cx<double> yv = Ys[h][k0 + k4][16 * tj + i16];
+        RR[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv.r, yv.r, RR[tj], 0, 0, 0);
+        II[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv.i, yv.i, II[tj], 0, 0, 0);
+        RI[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv.r, yv.i, RI[tj], 0, 0, 0);
+        IR[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv.i, yv.r, IR[tj], 0, 0, 0);
+      }
+    }
+  }
+  // conj(w) y = (RR + II, RI - IR); result row lane / 16 + 4 v, column lane % 16
+#pragma unroll
+  for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * ti + k4 + 4 * v, r = 16 * tj + i16;
+      if (a < ntv && r < ncol)
+        out[(size_t)(col0 + r) * ostr_r + (size_t)ci * ostr_b + h * ntv + a] =
+            mk(RR[tj][v] + II[tj][v], RI[tj][v] - IR[tj][v]);
+    }
+}
+
 // ---------------------------------------------------------- prolongation
 // x[r](site, k) = sum_a W_a(site, k) x_c[r](block, h(k), a).  Workgroup =
 // (block, group of KP spin-colour components of one chirality h), the group
@@ -695,6 +782,12 @@ void launch_restrict(cx<T>* out, size_t ostr_r, size_t ostr_b, const cx<T>* y, s
     if (nrhs >= RESTRICT_MFMA_MIN_RHS) {
       dim3 grid(g.nblocks, (nrhs + 31) / 32);
       restrict_mfma_kernel<S><<<grid, 256, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, nrhs, face_mu);
+      return;
+    }
+  } else if constexpr (std::is_same<S, double>::value) {
+    if (nrhs >= RESTRICT_MFMA64_MIN_RHS && g.ntv <= 32) {
+      dim3 grid(g.nblocks, (nrhs + 31) / 32);
+      restrict_mfma64_kernel<<<grid, 256, 0, st>>>(out, ostr_r, ostr_b, y, ystr, bv, g, nrhs, face_mu);
       return;
     }
   }

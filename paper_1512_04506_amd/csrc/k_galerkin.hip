@@ -15,10 +15,13 @@
 // A basis vector lives on one chirality, so P_mu w is two of its spins
 // multiplied by phases +-1, +-i: exact copies of stored values.  Per block
 // and direction this is a complex contraction of 2 ntv rows by 2 ntv
-// columns over 6 |F| terms, which runs on the matrix cores (FP32
-// 32x32x2 MFMA, one wave per (row chirality, column chirality) tile).  Chunks
-// of GC_CS face sites are staged through LDS; the loads of the next chunk are
-// issued before the matrix products of the current one.
+// columns over 6 |F| terms, which runs on the matrix cores, one wave per
+// (row chirality, column chirality) quadrant: FP32 32x32x2 MFMA, or FP64
+// 16x16x4 MFMA on four 16x16 tiles.  Chunks of face sites (8 in FP32, 4 in
+// FP64) are staged through LDS; the loads of the next chunk are issued
+// before the matrix products of the current one.
+#include <type_traits>
+
 #include "galerkin.h"
 
 namespace ddamg {
@@ -26,10 +29,14 @@ namespace ddamg {
 namespace {
 
 typedef float gc_v16 __attribute__((ext_vector_type(16)));
-constexpr int GC_CS = 8;             // face sites per chunk
-constexpr int GC_ROWS = 6 * GC_CS;   // contraction terms per chunk
-constexpr int GC_LD = 33;            // padded row length (float2) in LDS
-constexpr int GC_NQ = 4;             // (spin, chirality, vector) entries per thread and chunk
+typedef double gc_v4d __attribute__((ext_vector_type(4)));
+template <typename T>
+struct GcShape {
+  static constexpr int CS = sizeof(T) == 8 ? 4 : 8;  // face sites per chunk
+  static constexpr int ROWS = 6 * CS;                 // contraction terms per chunk
+  static constexpr int NQ = CS / 2;                   // (spin, chirality, vector) entries per thread and chunk
+};
+constexpr int GC_LD = 33;  // padded row length in LDS
 
 // P_mu w for w of chirality ch: component sg of the 2-spinor is
 // phase * w_spin.  ch = 0: (w_0, w_1).  ch = 1: -X_mu (w_2, w_3), i.e.
@@ -61,11 +68,12 @@ __device__ inline void proj_spin(int mu, int ch, int sg, int& spin, float& pr, f
 
 __device__ inline int sel4(const int a[4], int mu) { return mu == 0 ? a[0] : mu == 1 ? a[1] : mu == 2 ? a[2] : a[3]; }
 
-template <typename S>
-__global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restrict__ Dc, BasisView<S> bv,
-                                                             GaugeView<float> gv, Geom g) {
-  __shared__ float2 Ps[2][GC_ROWS][GC_LD];  // [row chirality][term][row vector]
-  __shared__ float2 Qs[2][GC_ROWS][GC_LD];  // [column chirality][term][column vector]
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<T>* __restrict__ Dc, BasisView<S> bv,
+                                                             GaugeView<T> gv, Geom g) {
+  constexpr int GC_CS = GcShape<T>::CS, GC_ROWS = GcShape<T>::ROWS, GC_NQ = GcShape<T>::NQ;
+  __shared__ cx<T> Ps[2][GC_ROWS][GC_LD];  // [row chirality][term][row vector]
+  __shared__ cx<T> Qs[2][GC_ROWS][GC_LD];  // [column chirality][term][column vector]
   // blocks in lexicographic order (through the XCD swizzle): the neighbour
   // blocks read here are processed at about the same time on the same XCD
   const int bl = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -84,8 +92,8 @@ __global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restri
 
   // raw values of one chunk: the basis at x (rows) and at x + mu (columns)
   // for GC_NQ (spin, chirality, vector) entries, and the link at x
-  cx<float> praw[GC_NQ][3], qraw[GC_NQ][3], uraw[3][3];
-  float psc[GC_NQ], qsc[GC_NQ];
+  cx<T> praw[GC_NQ][3], qraw[GC_NQ][3], uraw[3][3];
+  T psc[GC_NQ], qsc[GC_NQ];
   auto nsites_of = [&](int mu) { return g.vblock / sel4(g.bs, mu); };
   auto fetch = [&](int mu, int f0) {
     const int bsm = sel4(g.bs, mu);
@@ -100,10 +108,10 @@ __global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restri
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) uraw[a][b] = ldc<float>(gv.U + (size_t)(mu * 9 + 3 * a + b) * V, x);
+      for (int b = 0; b < 3; ++b) uraw[a][b] = ldc<T>(gv.U + (size_t)(mu * 9 + 3 * a + b) * V, x);
 #pragma unroll
     for (int q = 0; q < GC_NQ; ++q) {
-      const int r2 = rest + 32 * q;
+      const int r2 = rest + (256 / GC_CS) * q;
       const int sg = r2 & 1, ch = (r2 >> 1) & 1, av = min(r2 >> 2, ntv - 1);
       int spin;
       float pr, pi;
@@ -111,14 +119,14 @@ __global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restri
       const stc_t<S>* wb = bv.W + (size_t)(av * 12 + 3 * spin) * V;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        praw[q][c] = ldc<float>(wb + (size_t)c * V, x);
-        qraw[q][c] = ldc<float>(wb + (size_t)c * V, y);
+        praw[q][c] = ldc<T>(wb + (size_t)c * V, x);
+        qraw[q][c] = ldc<T>(wb + (size_t)c * V, y);
       }
       if constexpr (is_half<S>()) {
         psc[q] = bv.Wsc[(size_t)av * V + x];
         qsc[q] = bv.Wsc[(size_t)av * V + y];
       } else {
-        psc[q] = qsc[q] = 1.f;
+        psc[q] = qsc[q] = (T)1;
       }
     }
   };
@@ -126,29 +134,37 @@ __global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restri
     const bool fin = f0 + xl < nsites_of(mu);
 #pragma unroll
     for (int q = 0; q < GC_NQ; ++q) {
-      const int r2 = rest + 32 * q;
+      const int r2 = rest + (256 / GC_CS) * q;
       const int sg = r2 & 1, ch = (r2 >> 1) & 1, av = r2 >> 2;
       int spin;
       float pr, pi;
       proj_spin(mu, ch, sg, spin, pr, pi);
       const bool ok = fin && av < ntv;
+      const T tr = (T)pr, ti = (T)pi;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const cx<float> pv = psc[q] * praw[q][c];
-        cx<float> u = mk(0.f, 0.f);
+        const cx<T> pv = psc[q] * praw[q][c];
+        cx<T> u = mk((T)0, (T)0);
 #pragma unroll
         for (int b = 0; b < 3; ++b) u = cfma(uraw[c][b], qraw[q][b], u);
         u = qsc[q] * u;
         const int row = xl * 6 + sg * 3 + c;
-        Ps[ch][row][av] = ok ? make_float2(pr * pv.r - pi * pv.i, pr * pv.i + pi * pv.r) : make_float2(0.f, 0.f);
-        Qs[ch][row][av] = ok ? make_float2(pr * u.r - pi * u.i, pr * u.i + pi * u.r) : make_float2(0.f, 0.f);
+        Ps[ch][row][av] = ok ? mk(tr * pv.r - ti * pv.i, tr * pv.i + ti * pv.r) : mk((T)0, (T)0);
+        Qs[ch][row][av] = ok ? mk(tr * u.r - ti * u.i, tr * u.i + ti * u.r) : mk((T)0, (T)0);
       }
     }
   };
 
-  gc_v16 RR, II, RI, IR;
+  // FP32: one 32x32 tile per wave; FP64: four 16x16 tiles [ti][tj]
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int NACC = F64 ? 4 : 1;
+  using Acc = typename std::conditional<F64, gc_v4d, gc_v16>::type;
+  constexpr int AV = F64 ? 4 : 16;
+  Acc RR[NACC], II[NACC], RI[NACC], IR[NACC];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) RR[v] = II[v] = RI[v] = IR[v] = 0.f;
+  for (int u = 0; u < NACC; ++u)
+#pragma unroll
+    for (int v = 0; v < AV; ++v) RR[u][v] = II[u][v] = RI[u][v] = IR[u][v] = (T)0;
   int mu = 0, f0 = 0;
   fetch(0, 0);
   for (;;) {
@@ -161,25 +177,54 @@ __global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restri
     }
     if (nmu < 4) fetch(nmu, nf0);
     __syncthreads();
+    if constexpr (F64) {
+      const int i16 = lane & 15, k4 = lane >> 4;
 #pragma unroll
-    for (int tt = 0; tt < GC_ROWS / 2; ++tt) {
-      const float2 pv = Ps[h][2 * tt + kk][al];
-      const float2 qv = Qs[hp][2 * tt + kk][al];
-      RR = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.x, qv.x, RR, 0, 0, 0);
-      II = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.y, qv.y, II, 0, 0, 0);
-      RI = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.x, qv.y, RI, 0, 0, 0);
-      IR = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.y, qv.x, IR, 0, 0, 0);
+      for (int k0 = 0; k0 < GC_ROWS; k0 += 4) {
+        cx<T> pv[2], qv[2];
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2) {
+          pv[t2] = Ps[h][k0 + k4][16 * t2 + i16];
+          qv[t2] = Qs[hp][k0 + k4][16 * t2 + i16];
+        }
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) {
+            Acc* const acc[4] = {&RR[2 * ti + tj], &II[2 * ti + tj], &RI[2 * ti + tj], &IR[2 * ti + tj]};
+            *acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[ti].r, qv[tj].r, *acc[0], 0, 0, 0);
+            *acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[ti].i, qv[tj].i, *acc[1], 0, 0, 0);
+            *acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[ti].r, qv[tj].i, *acc[2], 0, 0, 0);
+            *acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[ti].i, qv[tj].r, *acc[3], 0, 0, 0);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int tt = 0; tt < GC_ROWS / 2; ++tt) {
+        const cx<T> pv = Ps[h][2 * tt + kk][al];
+        const cx<T> qv = Qs[hp][2 * tt + kk][al];
+        RR[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.r, qv.r, RR[0], 0, 0, 0);
+        II[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.i, qv.i, II[0], 0, 0, 0);
+        RI[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.r, qv.i, RI[0], 0, 0, 0);
+        IR[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv.i, qv.r, IR[0], 0, 0, 0);
+      }
     }
     if (nmu != mu) {
       // slot 1 + 2 mu done: sum conj(p) q = (RR + II, RI - IR)
-      const float coef = (mu == 3 && bc[3] == g.NB[3] - 1) ? 0.5f : -0.5f;
-      cx<float>* out = Dc + ((size_t)ci * 9 + 1 + 2 * mu) * nn + (size_t)(hp * ntv + al) * nc + h * ntv;
+      const T coef = (mu == 3 && bc[3] == g.NB[3] - 1) ? (T)0.5 : (T)-0.5;
+      cx<T>* out = Dc + ((size_t)ci * 9 + 1 + 2 * mu) * nn + h * ntv;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int ai = 8 * (v / 4) + 4 * kk + (v % 4);
-        if (ai < ntv && al < ntv) out[ai] = mk(coef * (RR[v] + II[v]), coef * (RI[v] - IR[v]));
-        RR[v] = II[v] = RI[v] = IR[v] = 0.f;
-      }
+      for (int u = 0; u < NACC; ++u)
+#pragma unroll
+        for (int v = 0; v < AV; ++v) {
+          // FP32 32x32 result: row 8 (v / 4) + 4 kk + v % 4, column lane % 32;
+          // FP64 16x16 result: row lane / 16 + 4 v, column lane % 16
+          const int ai = F64 ? 16 * (u >> 1) + (lane >> 4) + 4 * v : 8 * (v / 4) + 4 * kk + (v % 4);
+          const int aj = F64 ? 16 * (u & 1) + (lane & 15) : al;
+          if (ai < ntv && aj < ntv)
+            out[(size_t)(hp * ntv + aj) * nc + ai] = mk(coef * (RR[u][v] + II[u][v]), coef * (RI[u][v] - IR[u][v]));
+          RR[u][v] = II[u][v] = RI[u][v] = IR[u][v] = (T)0;
+        }
       if (nmu == 4) break;
     }
     mu = nmu;
@@ -189,15 +234,16 @@ __global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<float>* __restri
 
 }  // namespace
 
-template <typename S>
-void launch_galerkin_cross(cx<float>* Dc, const BasisView<S>& bv, const GaugeView<float>& gv, const Geom& g,
-                           hipStream_t st) {
-  galerkin_cross_kernel<S><<<g.nblocks, 256, 0, st>>>(Dc, bv, gv, g);
+template <typename T, typename S>
+void launch_galerkin_cross(cx<T>* Dc, const BasisView<S>& bv, const GaugeView<T>& gv, const Geom& g, hipStream_t st) {
+  galerkin_cross_kernel<T, S><<<g.nblocks, 256, 0, st>>>(Dc, bv, gv, g);
 }
 
-template void launch_galerkin_cross<float>(cx<float>*, const BasisView<float>&, const GaugeView<float>&, const Geom&,
-                                           hipStream_t);
-template void launch_galerkin_cross<__half>(cx<float>*, const BasisView<__half>&, const GaugeView<float>&,
-                                            const Geom&, hipStream_t);
+template void launch_galerkin_cross<float, float>(cx<float>*, const BasisView<float>&, const GaugeView<float>&,
+                                                  const Geom&, hipStream_t);
+template void launch_galerkin_cross<float, __half>(cx<float>*, const BasisView<__half>&, const GaugeView<float>&,
+                                                   const Geom&, hipStream_t);
+template void launch_galerkin_cross<double, double>(cx<double>*, const BasisView<double>&, const GaugeView<double>&,
+                                                    const Geom&, hipStream_t);
 
 }  // namespace ddamg

@@ -204,6 +204,136 @@ __global__ __launch_bounds__(TPB) void dslash_kernel(cx<Tout>* __restrict__ out,
   }
 }
 
+// The full operator with the block's input staged in LDS: workgroup = (one
+// block, group of NR rhs), one lane per site.  The block's spinors are read
+// once, coalesced, into LDS; a hop to a neighbour inside the block reads it
+// there, a hop leaving the block reads the neighbour block in global memory
+// (the lanes of a wave on a block face take that branch).  This keeps the
+// eight neighbour reads of every site out of the L2.
+template <int MU, bool FWD, int NR, typename Tin, typename Tc, typename S>
+__device__ inline void hop_staged(cx<Tc> acc[NR][4][3], const cx<Tin>* lds, int vb, int ln, bool inside,
+                                  const cx<Tin>* in, size_t rs, int nr, int sn, int slink, Tc sign,
+                                  const GaugeView<S>& gv, size_t V) {
+  cx<Tc> p[NR][4][3];
+  if (inside) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[r][sp][c] = cvt<Tc>(lds[(r * 12 + 3 * sp + c) * vb + ln]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const cx<Tin>* ir = in + (size_t)min(r, nr - 1) * rs;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[r][sp][c] = sign * cvt<Tc>(elem(ir + (size_t)(3 * sp + c) * V, (unsigned)sn));
+    }
+  }
+  hop_spinor_multi<MU, FWD, NR, Tc, S>(acc, p, gv, slink, V);
+}
+
+template <int MU, int NR, typename Tin, typename Tc, typename S>
+__device__ inline void hops_staged_mu(cx<Tc> acc[NR][4][3], const cx<Tin>* lds, int vb, const cx<Tin>* in, size_t rs,
+                                      int nr, const GaugeView<S>& gv, const Geom& g, const SitePos& p) {
+  const size_t V = g.V;
+  const int l = p.lc[MU];
+  const bool live = g.V > 0;  // opaque: each hop stays in its own region
+  if (live) {
+    const bool inside = l < g.bs[MU] - 1;
+    const bool wrap = MU == 3 && !inside && p.bc[3] == g.NB[3] - 1;
+    hop_staged<MU, true, NR, Tin, Tc, S>(acc, lds, vb, p.l + g.lstr[MU], inside, in, rs, nr,
+                                          inside ? p.S : nbr_fwd(g, p, MU), p.S, wrap ? (Tc)-1 : (Tc)1, gv, V);
+  }
+  asm volatile("" ::: "memory");
+  if (live) {
+    const bool inside = l > 0;
+    const bool wrap = MU == 3 && !inside && p.bc[3] == 0;
+    const int sb = nbr_bwd(g, p, MU);
+    hop_staged<MU, false, NR, Tin, Tc, S>(acc, lds, vb, p.l - g.lstr[MU], inside, in, rs, nr, sb, sb,
+                                           wrap ? (Tc)-1 : (Tc)1, gv, V);
+  }
+}
+
+template <typename Tin, typename Tout, typename S, typename Tc, int NR>
+__global__ __launch_bounds__(256) void dslash_staged_kernel(cx<Tout>* __restrict__ out, const cx<Tin>* __restrict__ in,
+                                                            GaugeView<S> gv, Geom g, size_t in_rs, size_t out_rs,
+                                                            int nrhs) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  const int vb = g.vblock;
+  cx<Tin>* lds = reinterpret_cast<cx<Tin>*>(smem_raw);  // [NR][12][vb]
+  const int ngroup = (nrhs + NR - 1) / NR;
+  const int wl = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int r0 = (wl % ngroup) * NR;
+  const int nr = min(NR, nrhs - r0);
+  const int bl = wl / ngroup;  // lexicographic block order
+  int bc[4];
+  bc[0] = bl % g.NB[0];
+  bc[1] = (bl / g.NB[0]) % g.NB[1];
+  bc[2] = (bl / (g.NB[0] * g.NB[1])) % g.NB[2];
+  bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
+  const int ci = block_to_int(g, bc);
+  const int l = threadIdx.x;
+  const bool act = l < vb;
+  const size_t V = g.V;
+  const int s = ci * vb + (act ? l : 0);
+  const cx<Tin>* ip = in + (size_t)r0 * in_rs;
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        lds[(r * 12 + k) * vb + l] = elem(ip + (size_t)min(r, nr - 1) * in_rs + (size_t)k * V, (unsigned)s);
+  }
+  __syncthreads();
+  if (!act) return;
+  const SitePos pos = site_pos(g, s);
+  cx<Tc> acc[NR][4][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[r][sp][k] = mk((Tc)0, (Tc)0);
+  {
+    cx<Tc> p[NR][4][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p[r][sp][k] = cvt<Tc>(lds[(r * 12 + 3 * sp + k) * vb + l]);
+    clover_apply_multi<NR, Tc, S>(acc, p, gv, s, V);
+  }
+  hops_staged_mu<0, NR, Tin, Tc, S>(acc, lds, vb, ip, in_rs, nr, gv, g, pos);
+  asm volatile("" ::: "memory");
+  hops_staged_mu<1, NR, Tin, Tc, S>(acc, lds, vb, ip, in_rs, nr, gv, g, pos);
+  asm volatile("" ::: "memory");
+  hops_staged_mu<2, NR, Tin, Tc, S>(acc, lds, vb, ip, in_rs, nr, gv, g, pos);
+  asm volatile("" ::: "memory");
+  hops_staged_mu<3, NR, Tin, Tc, S>(acc, lds, vb, ip, in_rs, nr, gv, g, pos);
+  cx<Tout>* op = out + (size_t)r0 * out_rs;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) break;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) op[(size_t)r * out_rs + (size_t)(3 * sp + k) * V + s] = cvt<Tout>(acc[r][sp][k]);
+  }
+}
+
+template <typename Tin, typename Tout, typename S, typename Tc, int NR>
+void launch_staged(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, size_t in_rs,
+                   size_t out_rs, hipStream_t st) {
+  const int threads = ((g.vblock + 63) / 64) * 64;
+  const size_t lds = (size_t)NR * 12 * g.vblock * sizeof(cx<Tin>);
+  const unsigned grid = (unsigned)g.nblocks * (unsigned)((nrhs + NR - 1) / NR);
+  dslash_staged_kernel<Tin, Tout, S, Tc, NR><<<grid, threads, lds, st>>>(out, in, gv, g, in_rs, out_rs, nrhs);
+}
+
 template <typename Tin, typename Tout, typename S, typename Tc, int MODE, int NR>
 void launch_mode(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mu, int chi_in,
                  size_t in_rs, size_t out_rs, size_t nsite, hipStream_t st) {
@@ -238,6 +368,14 @@ void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, con
                                                                       : (size_t)g.V;
   switch (mode) {
     case DS_FULL:
+      // blocks of up to 256 sites: the block-staged kernel, one or two rhs per lane
+      if (g.vblock <= 256) {
+        if (nrhs == 1)
+          launch_staged<Tin, Tout, S, Tc, 1>(out, in, gv, g, nrhs, in_rstride, out_rstride, st);
+        else
+          launch_staged<Tin, Tout, S, Tc, 2>(out, in, gv, g, nrhs, in_rstride, out_rstride, st);
+        break;
+      }
       launch_nr<Tin, Tout, S, Tc, DS_FULL>(out, in, gv, g, nrhs, mu, chi_in, in_rstride, out_rstride, nsite, st);
       break;
     case DS_BLOCK:

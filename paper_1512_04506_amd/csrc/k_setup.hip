@@ -30,8 +30,8 @@ constexpr int QR_LD = MAX_NTV + 1;   // padded LDS row
 //              tiles are summed through LDS.  Every entry of X is read once.
 //   G = T^H T: Cholesky (real positive diagonal) across the workgroup and
 //              T^{-1} by back substitution;
-//   X <- X T^{-1}: each lane updates the rows of its own site (coalesced,
-//              in place).
+//   X <- X T^{-1}: on the FP64 matrix cores, tiles of 16 sites x 16 test
+//              vectors (in place for the second pass).
 typedef double qr_v4d __attribute__((ext_vector_type(4)));
 
 template <typename Tin>
@@ -197,49 +197,70 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
   }
 }
 
-// Wout <- Xin T^{-1} on one aggregate (in place when Wout == Xin): lane =
-// site, T^{-1} (upper triangular) read from the Gram kernel's output into
-// LDS and used as broadcasts.
+// Wout <- Xin T^{-1} on the FP64 matrix cores (16x16x4 MFMA): per aggregate
+// W (rows = 16 consecutive sites of one component, columns = test vectors)
+// = X T^{-1}, T^{-1} (upper triangular, from the Gram kernel) in LDS, the rows of X loaded straight from memory (16
+// consecutive sites per lane group, coalesced).  The K loop runs over all 32
+// padded test vectors with clamped loads and zero factors, so all loads of a
+// tile are in flight together.  A wave finishes reading its row tile before
+// it writes it and no other wave touches those rows, so the update may run
+// in place.
 template <typename Tin>
-__global__ __launch_bounds__(QR_THREADS) void qr_update_kernel(cx<double>* Wout, const cx<Tin>* Xin, Geom g,
-                                                               const cx<double>* Tinv) {
-  __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];
+__global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* Wout, const cx<Tin>* Xin, Geom g,
+                                                                    const cx<double>* Tinv) {
+  __shared__ cx<double> Ti[MAX_NTV][MAX_NTV + 1];
   const int ci = blockIdx.x >> 1;
   const int h = blockIdx.x & 1;
   const int n = g.ntv;
   const size_t V = g.V;
-  const int l = threadIdx.x;
-  const bool act = l < g.vblock;
-  const bool two = n > 16;
-  const size_t site = (size_t)ci * g.vblock + (act ? l : 0);
+  const int vb = g.vblock;
+  const int l = threadIdx.x, lane = l & 63, w = l >> 6;
   const cx<double>* Tg = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
-  for (int e = l; e < n * n; e += blockDim.x) Ti[e / n][e % n] = Tg[e];
+  for (int e = l; e < MAX_NTV * MAX_NTV; e += blockDim.x) {
+    const int i = e / MAX_NTV, j = e % MAX_NTV;
+    Ti[i][j] = (i < n && j < n) ? Tg[i * n + j] : mk(0.0, 0.0);
+  }
   __syncthreads();
-  if (!act) return;
-  auto idx = [&](int a, int k) -> size_t { return ((size_t)a * 12 + 6 * h + k) * V + site; };
-  for (int k = 0; k < 6; ++k) {
-    // output columns in two halves of 16, so that 16 accumulators are
-    // live: columns 16..31 first (for n > 16; they read every input row),
-    // then 0..15, which read only rows 0..15, not yet overwritten.  Each
-    // lane reads and writes only its own site.
-    for (int jh = two ? 1 : 0; jh >= 0; --jh) {
-      cx<double> y[16];
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const size_t base = (size_t)ci * vb;
+  const int tiles_per_comp = (vb + 15) / 16;
+  const int ntile = 6 * tiles_per_comp;
+  for (int tile = w; tile < ntile; tile += QR_THREADS / 64) {
+    const int c = tile / tiles_per_comp, s0 = (tile % tiles_per_comp) * 16;
+    const int sa = min(s0 + i16, vb - 1);  // A operand: site of this lane's row (clamped)
+    cx<double> xa[MAX_NTV / 4];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) y[j] = mk(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < MAX_NTV; ++i) {
-        if (i < n && i < 16 * jh + 16) {
-          const cx<double> xi = cvt<double>(Xin[idx(i, k)]);
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (16 * jh + j >= i && 16 * jh + j < n) y[j] = cfma(xi, Ti[i][16 * jh + j], y[j]);
-        }
-        if ((i & 3) == 3) asm volatile("" ::: "memory");  // bound the loads in flight
-      }
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (16 * jh + j < n) Wout[idx(16 * jh + j, k)] = y[j];
+    for (int q = 0; q < MAX_NTV / 4; ++q) {
+      const int k = min(4 * q + k4, n - 1);
+      xa[q] = cvt<double>(Xin[((size_t)k * 12 + 6 * h + c) * V + base + sa]);
     }
+    qr_v4d RR[2], II[2], RI[2], IR[2];
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) RR[tj][v] = II[tj][v] = RI[tj][v] = IR[tj][v] = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAX_NTV / 4; ++q) {
+      const double f = 4 * q + k4 < n ? 1.0 : 0.0;  // padded test vectors add nothing
+      const double ar = f * xa[q].r, ai = f * xa[q].i;
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        const cx<double> b = Ti[4 * q + k4][16 * tj + i16];
+        RR[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.r, RR[tj], 0, 0, 0);
+        II[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.i, II[tj], 0, 0, 0);
+        RI[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.i, RI[tj], 0, 0, 0);
+        IR[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.r, IR[tj], 0, 0, 0);
+      }
+    }
+    // result row lane / 16 + 4 v (site), column lane % 16 (test vector)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int srow = s0 + k4 + 4 * v, j = 16 * tj + i16;
+        if (srow < vb && j < n)
+          Wout[((size_t)j * 12 + 6 * h + c) * V + base + srow] = mk(RR[tj][v] - II[tj][v], RI[tj][v] + IR[tj][v]);
+      }
   }
 }
 
@@ -286,9 +307,9 @@ void launch_aggregate_qr(cx<double>* W, const cx<Tin>* X, const Geom& g, int* st
                          hipStream_t st) {
   // CholQR2: pass 1 from X into W, pass 2 on W in place
   qr_gram_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(X, g, status, tws);
-  qr_update_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, X, g, tws);
+  qr_update_mfma_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, X, g, tws);
   qr_gram_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, status, tws);
-  qr_update_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, W, g, tws);
+  qr_update_mfma_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, W, g, tws);
 }
 template void launch_aggregate_qr<double>(cx<double>*, const cx<double>*, const Geom&, int*, cx<double>*,
                                           hipStream_t);

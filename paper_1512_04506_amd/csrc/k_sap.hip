@@ -2,9 +2,9 @@
 //
 // One workgroup per (block of the given colour, rhs); one thread per site of
 // the block.  The workgroup
-//   1. forms the residual r = y - D x on its sites (neighbour values from
-//      the other colour come from global memory and are not written in this
-//      phase, so there is no race),
+//   1. forms the residual r = y - D x on its sites (the block's x staged in
+//      LDS; neighbour values from the other colour come from global memory
+//      and are not written in this phase, so there is no race),
 //   2. runs n_mr minimal-residual steps on B e = r, where B is D restricted
 //      to the block (hops leaving the block dropped): the current residual
 //      rho lives in registers and is exchanged between sites through LDS,
@@ -72,27 +72,51 @@ __device__ inline void block_hops(cx<T> acc[NR][4][3], const cx<T>* lds, int vb,
   }
 }
 
-// hops of the full operator for NR vectors read from global memory
+// hops of the full operator for NR vectors whose in-block values are staged
+// in LDS: a neighbour inside the block is read there, one across the face
+// from global memory (the other colour's blocks, not written in this phase)
 template <int MU, int NR, typename T, typename S>
-__device__ inline void full_hops(cx<T> acc[NR][4][3], const cx<T>* x, size_t rs, int nr, const SitePos& p,
-                                 const Geom& g, const GaugeView<S>& gv, size_t V) {
-  // the run-time predicate (always true) keeps the compiler from hoisting
-  // the loads of both hops above either of them
-  const bool live = g.V > 0;
+__device__ inline void staged_hops(cx<T> acc[NR][4][3], const cx<T>* lds, int vb, const cx<T>* x, size_t rs, int nr,
+                                   const SitePos& p, const Geom& g, const GaugeView<S>& gv, size_t V) {
+  const bool live = g.V > 0;  // opaque: keeps each hop's loads with its arithmetic
   cx<T> q[NR][4][3];
   if (live) {
-    const int sn = nbr_fwd(g, p, MU);
-    const bool wrap = MU == 3 && p.lc[3] == g.bs[3] - 1 && p.bc[3] == g.NB[3] - 1;
+    const bool inside = p.lc[MU] < g.bs[MU] - 1;
+    if (inside) {
+      const int ln = p.l + g.lstr[MU];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) load_spinor<T, T, false>(q[r], x + (size_t)min(r, nr - 1) * rs, sn, V, -1, wrap ? (T)-1 : (T)1);
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) q[r][sp][k] = lds[(r * 12 + 3 * sp + k) * vb + ln];
+    } else {
+      const int sn = nbr_fwd(g, p, MU);
+      const bool wrap = MU == 3 && p.bc[3] == g.NB[3] - 1;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        load_spinor<T, T, false>(q[r], x + (size_t)min(r, nr - 1) * rs, sn, V, -1, wrap ? (T)-1 : (T)1);
+    }
     hop_spinor_multi<MU, true, NR, T, S>(acc, q, gv, p.S, V);
   }
   asm volatile("" ::: "memory");
   if (live) {
+    const bool inside = p.lc[MU] > 0;
     const int sb = nbr_bwd(g, p, MU);
-    const bool wrap = MU == 3 && p.lc[3] == 0 && p.bc[3] == 0;
+    if (inside) {
+      const int ln = p.l - g.lstr[MU];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) load_spinor<T, T, false>(q[r], x + (size_t)min(r, nr - 1) * rs, sb, V, -1, wrap ? (T)-1 : (T)1);
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) q[r][sp][k] = lds[(r * 12 + 3 * sp + k) * vb + ln];
+    } else {
+      const bool wrap = MU == 3 && p.bc[3] == 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        load_spinor<T, T, false>(q[r], x + (size_t)min(r, nr - 1) * rs, sb, V, -1, wrap ? (T)-1 : (T)1);
+    }
     hop_spinor_multi<MU, false, NR, T, S>(acc, q, gv, sb, V);
   }
 }
@@ -134,26 +158,37 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
         rho[r][sp][k] = mk((T)0, (T)0);
         e[r][sp][k] = mk((T)0, (T)0);
       }
+  // residual r = y - D x with the current x: the block's x is staged in LDS
+  // (the buffer the MR steps use later) for the in-block hops, the halo from
+  // the other colour comes from global memory; a missing second rhs repeats
+  // the first and is never stored
   if (act) {
-    // residual r = y - D x with the current x (global memory); a missing
-    // second rhs repeats the first and is never stored
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        lds[(r * 12 + k) * vb + l] = elem(x + (size_t)min(r, nr - 1) * rs + (size_t)k * V, (unsigned)s);
+  }
+  __syncthreads();
+  if (act) {
     cx<T> acc[NR][4][3], p[NR][4][3];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) acc[r][sp][k] = mk((T)0, (T)0);
-      load_spinor<T, T, false>(p[r], x + (size_t)min(r, nr - 1) * rs, s, V, -1, (T)1);
-    }
+        for (int k = 0; k < 3; ++k) {
+          acc[r][sp][k] = mk((T)0, (T)0);
+          p[r][sp][k] = lds[(r * 12 + 3 * sp + k) * vb + l];
+        }
     clover_apply_multi<NR, T, S>(acc, p, gv, s, V);
-    full_hops<0, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    staged_hops<0, NR, T, S>(acc, lds, vb, x, rs, nr, pos, g, gv, V);
     asm volatile("" ::: "memory");
-    full_hops<1, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    staged_hops<1, NR, T, S>(acc, lds, vb, x, rs, nr, pos, g, gv, V);
     asm volatile("" ::: "memory");
-    full_hops<2, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    staged_hops<2, NR, T, S>(acc, lds, vb, x, rs, nr, pos, g, gv, V);
     asm volatile("" ::: "memory");
-    full_hops<3, NR, T, S>(acc, x, rs, nr, pos, g, gv, V);
+    staged_hops<3, NR, T, S>(acc, lds, vb, x, rs, nr, pos, g, gv, V);
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -163,6 +198,7 @@ __global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, c
           rho[r][sp][k] = elem(y + (size_t)min(r, nr - 1) * rs + (size_t)(3 * sp + k) * V, (unsigned)s) - acc[r][sp][k];
   }
 
+  __syncthreads();  // every lane is done reading the staged x
   for (int it = 0; it < n_mr; ++it) {
     // Launder an offset of the link/clover pointers: the loads of B below are
     // the same in every MR step, and hoisting them out of the loop would pin

@@ -121,8 +121,10 @@ __device__ inline void staged_hops(cx<T> acc[NR][4][3], const cx<T>* lds, int vb
   }
 }
 
+// At least two waves per SIMD: the FP64 instance would otherwise take 262
+// registers and run one wave per SIMD (the FP32 ones are below 256 anyway).
 template <typename T, typename S, int NR>
-__global__ __launch_bounds__(256) void sap_phase_kernel(cx<T>* __restrict__ x, const cx<T>* __restrict__ y,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sap_phase_kernel(cx<T>* __restrict__ x, const cx<T>* __restrict__ y,
                                                         GaugeView<S> gv, Geom g, int colour, int n_mr, size_t rs,
                                                         int nrhs) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];

@@ -68,8 +68,9 @@ __device__ inline void proj_spin(int mu, int ch, int sg, int& spin, float& pr, f
 
 __device__ inline int sel4(const int a[4], int mu) { return mu == 0 ? a[0] : mu == 1 ? a[1] : mu == 2 ? a[2] : a[3]; }
 
+// two waves per SIMD (the FP64 instance would otherwise take 280 registers)
 template <typename T, typename S>
-__global__ __launch_bounds__(256) void galerkin_cross_kernel(cx<T>* __restrict__ Dc, BasisView<S> bv,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void galerkin_cross_kernel(cx<T>* __restrict__ Dc, BasisView<S> bv,
                                                              GaugeView<T> gv, Geom g) {
   constexpr int GC_CS = GcShape<T>::CS, GC_ROWS = GcShape<T>::ROWS, GC_NQ = GcShape<T>::NQ;
   __shared__ cx<T> Ps[2][GC_ROWS][GC_LD];  // [row chirality][term][row vector]

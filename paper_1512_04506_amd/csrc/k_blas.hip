@@ -371,8 +371,18 @@ void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>
   if (nrhs <= 0 || nvec <= 0 || nvec > GS_FUSED_MAXV) return;
   const int nchunk = blas_nchunks(n);
   const size_t chunk = (n + nchunk - 1) / nchunk;
-  gs_fused_kernel<GS_FUSED_MAXV><<<dim3(nchunk, nrhs), BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n,
-                                                                    chunk, nchunk, active);
+  // the narrowest instance that holds nvec basis entries per element (fewer
+  // registers, more waves in flight for this streaming kernel)
+  const dim3 grid(nchunk, nrhs);
+  if (nvec <= 4)
+    gs_fused_kernel<4><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active);
+  else if (nvec <= 8)
+    gs_fused_kernel<8><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active);
+  else if (nvec <= 16)
+    gs_fused_kernel<16><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active);
+  else
+    gs_fused_kernel<GS_FUSED_MAXV><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk,
+                                                        active);
   mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
 }
 

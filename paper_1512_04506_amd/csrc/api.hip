@@ -306,16 +306,15 @@ struct Solver final : SolverBase {
   DevBuf fy, fx;
   // setup workspace, allocated at the first setup and kept: FP64 copy of
   // the test vectors for the Gram-Schmidt, dequantised basis, D_c
-  // accumulation buffer and one chunk of D_ij P_j columns
+  // accumulation buffer and the block operator applied to the basis columns
   DevBuf ws_Wd, ws_Wt, ws_D, ws_Z, ws_T;
-  static constexpr int GAL_CHUNK = 32;  // all test vectors of one chirality per pass
   void ensure_setup_ws() {
     if (ws_Wd.p) return;
     ws_Wd.alloc<cx<double>>((size_t)g.ntv * fsz());
     ws_T.alloc<cx<double>>((size_t)2 * g.nblocks * QR_TWS_PER_AGG);
     if (is_half<S>()) ws_Wt.alloc<cx<T>>((size_t)g.ntv * fsz());  // else the stored basis is already cx<T>
     ws_D.alloc<cx<T>>((size_t)g.nblocks * 9 * g.nc * g.nc);
-    ws_Z.alloc<cx<T>>((size_t)std::min(g.ntv, GAL_CHUNK) * fsz());
+    ws_Z.alloc<cx<T>>((size_t)g.ntv * fsz());
   }
   // coarse work vectors (T)
   DevBuf yc, xc, te, ue, bo, cw, cV;
@@ -523,31 +522,19 @@ struct Solver final : SolverBase {
     } else {
       Wtp = reinterpret_cast<const cx<T>*>(Wq.get<stc_t<S>>());
     }
-    const int CH = std::min(g.ntv, (int)GAL_CHUNK);
+    // self slot: per chirality the block operator applied to all N_tv basis
+    // columns, restricted; forward crossing slots: one fused contraction of
+    // the basis (ntv <= 32 is validated at creation); backward slots by
+    // Eq. (dagger)
     cx<T>* Zp = ws_Z.get<cx<T>>();
-    // with up to 32 test vectors the block-crossing pieces come from one
-    // fused contraction of the basis (no D P field); otherwise every piece
-    // is D applied to the basis, then restricted
-    const bool fused_cross = g.ntv <= GALERKIN_CROSS_MAX_NTV;
-    const int npiece = fused_cross ? 1 : 5;
-    for (int hp = 0; hp < 2; ++hp)
-      for (int a0 = 0; a0 < g.ntv; a0 += CH) {
-        const int na = std::min(CH, g.ntv - a0);
-        const cx<T>* in = Wtp + (size_t)a0 * fsz();
-        for (int piece = 0; piece < npiece; ++piece) {
-          const int mode = piece == 0 ? DS_BLOCK : DS_CROSS_FWD;
-          const int mu = piece == 0 ? 0 : piece - 1;
-          const int slot = piece == 0 ? 0 : 1 + 2 * mu;
-          cx<T>* out = D + (size_t)slot * nn + (size_t)(hp * g.ntv + a0) * nc;
-          c->timed(DDAMG_KERNEL_SETUP_GALERKIN, na, [&] {
-            launch_dslash<T, T, T, T>(Zp, in, gva, g, na, mode, mu, hp, fsz(), fsz(), st);
-            // a block-crossing piece lives on the last layer of the block only
-            launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, na, st, piece == 0 ? -1 : mu);
-          });
-        }
-      }
-    if (fused_cross)
-      c->timed(DDAMG_KERNEL_SETUP_GALERKIN, 2 * g.ntv, [&] { launch_galerkin_cross<T, S>(D, bv(), gva, g, st); });
+    for (int hp = 0; hp < 2; ++hp) {
+      cx<T>* out = D + (size_t)(hp * g.ntv) * nc;  // slot 0, columns of chirality hp
+      c->timed(DDAMG_KERNEL_SETUP_GALERKIN, g.ntv, [&] {
+        launch_dslash<T, T, T, T>(Zp, Wtp, gva, g, g.ntv, DS_BLOCK, 0, hp, fsz(), fsz(), st);
+        launch_restrict<T, S>(out, nc, 9 * nn, Zp, fsz(), bv(), g, g.ntv, st);
+      });
+    }
+    c->timed(DDAMG_KERNEL_SETUP_GALERKIN, 2 * g.ntv, [&] { launch_galerkin_cross<T, S>(D, bv(), gva, g, st); });
     launch_dagger_fill<T>(D, c->nbr.get<int>(), g, st);
     launch_quantize_coarse<T, S>(Dq.get<stc_t<S>>(), Dsc.get<float>(), D, g, st);
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));

@@ -193,41 +193,41 @@ __global__ __launch_bounds__(256) void restrict_mfma_kernel(cx<float>* __restric
 #pragma unroll
   for (int v = 0; v < 16; ++v) RR[v] = II[v] = RI[v] = IR[v] = 0.f;
   const int a = lane & 31, kk = lane >> 5;
-  const int nW = 12 * ntv * RM_CS, nY = 12 * ncol * RM_CS;
-  // basis: element (a, comp, site), rhs: element (rhs, comp, site), the
-  // site fastest.  The loads of chunk f0 + RM_CS are issued (unconditionally,
-  // at clamped addresses) before the MFMAs consume chunk f0 from LDS; masks
-  // and scales are applied when the values are stored to LDS.
-  constexpr int NQ = (12 * 32 * RM_CS + 255) / 256;
-  cx<float> wraw[NQ], yraw[NQ];
-  float sraw[NQ];
+  // staging: lane (site xl of the chunk, test vector / rhs index idx) loads
+  // all 12 components of its basis vector and of its rhs at that site (the
+  // scale once); lanes 8 apart in idx, consecutive in xl, so each load is
+  // 8-site runs
+  static_assert(RM_CS * 32 == 256, "one (site, index) pair per lane");
+  const int xl = l % RM_CS, idx = l / RM_CS;
+  const bool wok = idx < ntv, yok = idx < ncol;
+  const int ia = min(idx, ntv - 1), ir = min(idx, ncol - 1);
+  stc_t<S> wraw[12];
+  cx<float> yraw[12];
+  float sraw = 1.f;
   auto fetch = [&](int f0) {
+    const int f = min(f0 + xl, nsites - 1);
+    const unsigned x = (unsigned)(base + (face_mu < 0 ? f : face_site(g, face_mu, g.bs[face_mu] - 1, f)));
+    const stc_t<S>* wb = bv.W + (size_t)ia * 12 * V;
+    const cx<float>* yb = y + (size_t)(col0 + ir) * ystr;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int e = l + 256 * q;
-      const int xl = e % RM_CS, rest = e / RM_CS, comp = rest % 12, idx = rest / 12;
-      const int f = min(f0 + xl, nsites - 1);
-      const size_t x = base + (face_mu < 0 ? f : face_site(g, face_mu, g.bs[face_mu] - 1, f));
-      const int ia = min(idx, ntv - 1), ir = min(idx, ncol - 1);
-      wraw[q] = ldc<float>(bv.W, ((size_t)ia * 12 + comp) * V + x);
-      if constexpr (is_half<S>()) sraw[q] = bv.Wsc[(size_t)ia * V + x];
-      yraw[q] = y[(size_t)(col0 + ir) * ystr + (size_t)comp * V + x];
+    for (int comp = 0; comp < 12; ++comp) {
+      wraw[comp] = elem(wb + (size_t)comp * V, x);
+      yraw[comp] = elem(yb + (size_t)comp * V, x);
     }
+    if constexpr (is_half<S>()) sraw = elem(bv.Wsc + (size_t)ia * V, x);
   };
   fetch(0);
   for (int f0 = 0; f0 < nsites; f0 += RM_CS) {
     __syncthreads();  // previous chunk consumed (and the zero fill done)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int e = l + 256 * q;
-      const int xl = e % RM_CS, rest = e / RM_CS, comp = rest % 12, idx = rest / 12;
+    {
       const bool fin = f0 + xl < nsites;
-      float sc = 1.f;
-      if constexpr (is_half<S>()) sc = sraw[q];
-      const float2 wv = fin ? make_float2(sc * wraw[q].r, sc * wraw[q].i) : make_float2(0.f, 0.f);
-      const float2 yv = fin ? make_float2(yraw[q].r, yraw[q].i) : make_float2(0.f, 0.f);
-      if (e < nW) Ws[comp / 6][xl * 6 + comp % 6][idx] = wv;
-      if (e < nY) Ys[comp / 6][xl * 6 + comp % 6][idx] = yv;
+#pragma unroll
+      for (int comp = 0; comp < 12; ++comp) {
+        const cx<float> wv = ldc<float>(&wraw[comp], (size_t)0);
+        Ws[comp / 6][xl * 6 + comp % 6][idx] =
+            (fin && wok) ? make_float2(sraw * wv.r, sraw * wv.i) : make_float2(0.f, 0.f);
+        Ys[comp / 6][xl * 6 + comp % 6][idx] = (fin && yok) ? make_float2(yraw[comp].r, yraw[comp].i) : make_float2(0.f, 0.f);
+      }
     }
     if (f0 + RM_CS < nsites) fetch(f0 + RM_CS);
     __syncthreads();

@@ -275,8 +275,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the lattice would be split "
-              "along t across GPUs with halo exchange; see the design notes). Run with --gpus 1.",
+        print("bench.py measures one GPU: the library has no multi-GPU path (a multi-GPU run would split "
+              "the lattice along t, with halo exchanges and all-reduced inner products). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
     import torch

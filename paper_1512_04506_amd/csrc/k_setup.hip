@@ -3,8 +3,8 @@
 // the resulting basis.
 //
 // The paper uses classical block Gram-Schmidt for fewer global sums and
-// better cache reuse.  Here each aggregate (block, chirality h: 6 V_block
-// rows, ntv columns) is one workgroup running CholQR2 in FP64: the Gram
+// better cache reuse.  Here every aggregate (block, chirality h: 6 V_block
+// rows, ntv columns) runs CholQR2 in FP64, all aggregates at once: the Gram
 // matrix X^H X, its Cholesky factor (positive real diagonal) and X <- X T^{-1};
 // doing it twice restores orthogonality to rounding.  The result is the
 // unique Q of X = Q T with positive diag(T), i.e. the basis Gram-Schmidt
@@ -20,25 +20,26 @@ constexpr int MAX_NTV = 32;
 constexpr int QR_CS = 8;             // sites per staged chunk of the Gram matrix pass
 constexpr int QR_ROWS = QR_CS * 6;   // rows (site, spin-colour) per chunk
 constexpr int QR_LD = MAX_NTV + 1;   // padded LDS row
-// One workgroup per aggregate (internal block ci, chirality h): rows are the
-// 6 V_block (spin of chirality h x colour, site) entries, columns the ntv
-// test vectors.  Per CholQR pass:
+// An aggregate is (internal block ci, chirality h): rows are the 6 V_block
+// (spin of chirality h x colour, site) entries, columns the ntv test
+// vectors.  Per CholQR pass, three kernels with one workgroup per aggregate:
 //   G = X^H X: on the FP64 matrix cores.  A 16x16x4 f64 MFMA takes, in lane
 //              l, entry (row l/16, column l%16) of a 4-row slice for both of
 //              its operands, so one load per lane and column tile feeds all
 //              of Re/Im X^T X; the waves split the rows and their partial
 //              tiles are summed through LDS.  Every entry of X is read once.
-//   G = T^H T: Cholesky (real positive diagonal) across the workgroup and
-//              T^{-1} by back substitution;
+//              G goes to the per-aggregate workspace.  The kernel holds no
+//              LDS beyond its staging buffer, so several aggregates share a
+//              compute unit and keep enough loads in flight.
+//   G = T^H T: Cholesky (real positive diagonal) and T^{-1} by back
+//              substitution, one 64-lane workgroup per aggregate on an
+//              ntv x (ntv+1) LDS matrix; T^{-1} replaces G in the workspace;
 //   X <- X T^{-1}: on the FP64 matrix cores, tiles of 16 sites x 16 test
 //              vectors (in place for the second pass).
 typedef double qr_v4d __attribute__((ext_vector_type(4)));
 
 template <typename Tin>
-__global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, Geom g, int* status,
-                                                             cx<double>* Tinv) {
-  __shared__ cx<double> G[MAX_NTV][MAX_NTV];
-  __shared__ cx<double> Ti[MAX_NTV][MAX_NTV];  // T^{-1}, upper triangular
+__global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, Geom g, cx<double>* Gout) {
   // the staged rows of the Gram matrix pass, later the partial tiles of two
   // waves
   constexpr size_t STAGE_BYTES = sizeof(cx<double>) * QR_ROWS * QR_LD > sizeof(qr_v4d) * 2 * 6 * 64
@@ -47,165 +48,180 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
   __shared__ __attribute__((aligned(32))) char stage_raw[STAGE_BYTES];
   auto Xs = reinterpret_cast<cx<double>(*)[QR_LD]>(stage_raw);
   auto part = reinterpret_cast<qr_v4d(*)[6][64]>(stage_raw);
-  __shared__ int fail;
   const int ci = blockIdx.x >> 1;  // internal block: its sites are ci * vblock + [0, vblock)
   const int h = blockIdx.x & 1;
   const int n = g.ntv;
   const size_t V = g.V;
   const int vb = g.vblock;
   const int l = threadIdx.x, lane = l & 63, w = l >> 6;
-  const bool act = l < vb;
-  const size_t site = (size_t)ci * vb + (act ? l : 0);
   const size_t base = (size_t)ci * vb;
-  const bool two = n > 16;           // second column tile (columns 16..31)
+  const bool two = n > 16;  // second column tile (columns 16..31)
   const int col0 = lane & 15, rsub = lane >> 4;
-  {
-    // tiles: 0 = Re(0,0) 1 = Im(0,0) 2 = Re(0,1) 3 = Im(0,1) 4 = Re(1,1) 5 = Im(1,1)
-    qr_v4d acc[6];
+  // tiles: 0 = Re(0,0) 1 = Im(0,0) 2 = Re(0,1) 3 = Im(0,1) 4 = Re(1,1) 5 = Im(1,1)
+  qr_v4d acc[6];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
-    // Rows (site, spin-colour) of QR_CS sites at a time are staged in LDS
-    // with coalesced loads (QR_CS consecutive sites of one test vector and
-    // component per 128-byte line); the next chunk's loads are in flight
-    // while the MFMAs consume the current one.
-    constexpr int NQ = QR_ROWS * 32 / 256;
-    cx<double> xq[NQ];
-    auto fetch = [&](int s0) {
+  for (int t = 0; t < 6; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
+  // Rows (site, spin-colour) of QR_CS sites at a time are staged in LDS with
+  // coalesced loads (QR_CS consecutive sites of one test vector and
+  // component); the next chunk's loads are in flight while the MFMAs consume
+  // the current one.  Padded test vectors (a >= ntv) are not loaded.
+  constexpr int NQ = QR_ROWS * 32 / 256;
+  cx<double> xq[NQ];
+  auto fetch = [&](int s0) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int e = l + 256 * q;
-        const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
-        const int sx = min(s0 + sl, vb - 1), ax = min(a, n - 1);
-        xq[q] = cvt<double>(W[((size_t)ax * 12 + 6 * h + c) * V + base + sx]);
-      }
-    };
-    fetch(0);
-    for (int s0 = 0; s0 < vb; s0 += QR_CS) {
-      __syncthreads();  // the previous chunk has been consumed
+    for (int q = 0; q < NQ; ++q) {
+      const int e = l + 256 * q;
+      const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
+      const int sx = min(s0 + sl, vb - 1);
+      xq[q] = a < n ? cvt<double>(W[((size_t)a * 12 + 6 * h + c) * V + base + sx]) : mk(0.0, 0.0);
+    }
+  };
+  fetch(0);
+  for (int s0 = 0; s0 < vb; s0 += QR_CS) {
+    __syncthreads();  // the previous chunk has been consumed
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int e = l + 256 * q;
-        const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
-        Xs[sl * 6 + c][a] = (s0 + sl < vb && a < n) ? xq[q] : mk(0.0, 0.0);
-      }
-      if (s0 + QR_CS < vb) fetch(s0 + QR_CS);
-      __syncthreads();
-      // 4-row slices; the two products feeding one accumulator are issued
-      // apart so no MFMA waits on the one before it
-      for (int t = w; t < QR_ROWS / 4; t += 4) {
-        const cx<double> y0 = Xs[4 * t + rsub][col0];
-        if (two) {
-          const cx<double> y1 = Xs[4 * t + rsub][16 + col0];
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.r, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.i, acc[3], 0, 0, 0);
-          acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.r, acc[4], 0, 0, 0);
-          acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.i, acc[5], 0, 0, 0);
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y1.i, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y1.r, acc[3], 0, 0, 0);
-          acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.i, y1.i, acc[4], 0, 0, 0);
-          acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1.i, y1.r, acc[5], 0, 0, 0);
-        } else {
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
-        }
+    for (int q = 0; q < NQ; ++q) {
+      const int e = l + 256 * q;
+      const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
+      Xs[sl * 6 + c][a] = s0 + sl < vb ? xq[q] : mk(0.0, 0.0);
+    }
+    if (s0 + QR_CS < vb) fetch(s0 + QR_CS);
+    __syncthreads();
+    // 4-row slices; the two products feeding one accumulator are issued
+    // apart so no MFMA waits on the one before it
+    for (int t = w; t < QR_ROWS / 4; t += 4) {
+      const cx<double> y0 = Xs[4 * t + rsub][col0];
+      if (two) {
+        const cx<double> y1 = Xs[4 * t + rsub][16 + col0];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.r, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.i, acc[3], 0, 0, 0);
+        acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.r, acc[4], 0, 0, 0);
+        acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.r, y1.i, acc[5], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y1.i, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y1.r, acc[3], 0, 0, 0);
+        acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.i, y1.i, acc[4], 0, 0, 0);
+        acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1.i, y1.r, acc[5], 0, 0, 0);
+      } else {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
       }
     }
-    __syncthreads();  // the staging buffer is reused for the partial tiles
-    // sum the four waves' tiles: waves 2,3 hand theirs to waves 0,1, then
-    // wave 1 to wave 0, which writes G (upper triangle and the (1,0) tile
-    // never read)
-    if (w >= 2)
+  }
+  __syncthreads();  // the staging buffer is reused for the partial tiles
+  // sum the four waves' tiles: waves 2,3 hand theirs to waves 0,1, then wave 1
+  // to wave 0, which writes the upper tiles of G (row-major, stride MAX_NTV)
+  if (w >= 2)
 #pragma unroll
-      for (int t = 0; t < 6; ++t) part[w - 2][t][lane] = acc[t];
-    __syncthreads();
-    if (w < 2)
+    for (int t = 0; t < 6; ++t) part[w - 2][t][lane] = acc[t];
+  __syncthreads();
+  if (w < 2)
 #pragma unroll
-      for (int t = 0; t < 6; ++t) acc[t] += part[w][t][lane];
-    __syncthreads();
-    if (w == 1)
+    for (int t = 0; t < 6; ++t) acc[t] += part[w][t][lane];
+  __syncthreads();
+  if (w == 1)
 #pragma unroll
-      for (int t = 0; t < 6; ++t) part[0][t][lane] = acc[t];
-    __syncthreads();
-    if (w == 0) {
+    for (int t = 0; t < 6; ++t) part[0][t][lane] = acc[t];
+  __syncthreads();
+  if (w == 0) {
 #pragma unroll
-      for (int t = 0; t < 6; ++t) acc[t] += part[0][t][lane];
+    for (int t = 0; t < 6; ++t) acc[t] += part[0][t][lane];
+    cx<double>* G = Gout + (size_t)blockIdx.x * QR_TWS_PER_AGG;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = rsub + 4 * v, j = col0;  // f64 16x16x4 result: row l/16 + 4v, column l%16
-        if (i < n && j < n) G[i][j] = mk(acc[0][v], acc[1][v]);
-        if (two) {
-          if (i < n && 16 + j < n) G[i][16 + j] = mk(acc[2][v], acc[3][v]);
-          if (16 + i < n && 16 + j < n) G[16 + i][16 + j] = mk(acc[4][v], acc[5][v]);
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int i = rsub + 4 * v, j = col0;  // f64 16x16x4 result: row l/16 + 4v, column l%16
+      if (i < n && j < n) G[i * MAX_NTV + j] = mk(acc[0][v], acc[1][v]);
+      if (two) {
+        if (i < n && 16 + j < n) G[i * MAX_NTV + 16 + j] = mk(acc[2][v], acc[3][v]);
+        if (16 + i < n && 16 + j < n) G[(16 + i) * MAX_NTV + 16 + j] = mk(acc[4][v], acc[5][v]);
       }
     }
+  }
+}
+
+// Cholesky G = T^H T (T upper, real positive diagonal) and T^{-1} of one
+// aggregate per 64-lane workgroup.  G (upper triangle, stride MAX_NTV) is
+// read from the workspace into an n x (n+1) LDS matrix; T overwrites its
+// upper triangle and the strictly upper part of T^{-1} is kept transposed in
+// the free lower triangle, its diagonal in dg.  T^{-1} (n x n, row-major)
+// replaces G in the workspace; a pivot that is not positive sets *status
+// and leaves zeros.
+__global__ __launch_bounds__(64) void qr_chol_kernel(cx<double>* tws, Geom g, int* status) {
+  extern __shared__ cx<double> sh[];
+  __shared__ double dg[MAX_NTV];
+  __shared__ int fail;
+  const int n = g.ntv, ld = n + 1;
+  const int l = threadIdx.x;
+  cx<double>* Tg = tws + (size_t)blockIdx.x * QR_TWS_PER_AGG;
+  for (int e = l; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    if (j >= i) sh[i * ld + j] = Tg[i * MAX_NTV + j];
+  }
+  if (l == 0) fail = 0;
+  __syncthreads();
+  // right-looking: step k scales row k by the pivot and updates the
+  // trailing upper triangle, its entries spread over the lanes
+  for (int k = 0; k < n; ++k) {
+    const double dk = sh[k * ld + k].r;  // every lane reads the same pivot
+    if (!(dk > 0.0)) {
+      if (l == 0) fail = 1;
+      break;
+    }
+    const double d = sqrt(dk);
     __syncthreads();
-    // Cholesky G = T^H T (T upper, real positive diagonal), right-looking,
-    // in place in the upper triangle of G: step k scales row k by the pivot
-    // and updates the trailing upper triangle, its entries spread over the
-    // workgroup
-    if (l == 0) fail = 0;
+    for (int j = k + l; j < n; j += 64) sh[k * ld + j] = j == k ? mk(d, 0.0) : (1.0 / d) * sh[k * ld + j];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-      const double dk = G[k][k].r;  // every thread reads the same pivot
-      if (!(dk > 0.0)) {
-        if (l == 0) fail = 1;
-        break;
-      }
-      const double d = sqrt(dk);
-      __syncthreads();
-      for (int j = k + l; j < n; j += blockDim.x) G[k][j] = j == k ? mk(d, 0.0) : (1.0 / d) * G[k][j];
-      __syncthreads();
-      const int m = n - k - 1;  // trailing size
-      for (int p = l; p < m * m; p += blockDim.x) {
-        const int i = k + 1 + p / m, j = k + 1 + p % m;
-        if (j >= i) G[i][j] = G[i][j] - cmulc(G[k][i], G[k][j]);
-      }
-      __syncthreads();
+    const int m = n - k - 1;  // trailing size
+    for (int p = l; p < m * m; p += 64) {
+      const int i = k + 1 + p / m, j = k + 1 + p % m;
+      if (j >= i) sh[i * ld + j] = sh[i * ld + j] - cmulc(sh[k * ld + i], sh[k * ld + j]);
     }
     __syncthreads();
-    if (fail) {
-      if (l == 0) atomicExch(status, 1);
-      cx<double>* To = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
-      for (int e = l; e < n * n; e += blockDim.x) To[e] = mk(0.0, 0.0);
-      return;
-    }
-    // T^{-1} by back substitution, one column per lane
-    if (l < n) {
-      const int j = l;
-      for (int i = j + 1; i < n; ++i) Ti[i][j] = mk(0.0, 0.0);
-      Ti[j][j] = mk(1.0 / G[j][j].r, 0.0);
+  }
+  __syncthreads();
+  if (fail) {
+    if (l == 0) atomicExch(status, 1);
+    for (int e = l; e < n * n; e += 64) Tg[e] = mk(0.0, 0.0);
+    return;
+  }
+  // T^{-1} by back substitution, one column j per lane: entry (i, j), i < j,
+  // lives at sh[j][i]; lane j reads T (i < mm) and its own column only
+  if (l < n) {
+    const int j = l;
+    dg[j] = 1.0 / sh[j * ld + j].r;
 #pragma unroll 1
-      for (int i = j - 1; i >= 0; --i) {
-        cx<double> vv = mk(0.0, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      cx<double> vv = mk(0.0, 0.0);
 #pragma unroll 1
-        for (int mm = i + 1; mm <= j; ++mm) vv = cfma(G[i][mm], Ti[mm][j], vv);
-        Ti[i][j] = (-1.0 / G[i][i].r) * vv;
-      }
+      for (int mm = i + 1; mm < j; ++mm) vv = cfma(sh[i * ld + mm], sh[j * ld + mm], vv);
+      vv = cfma(sh[i * ld + j], mk(dg[j], 0.0), vv);
+      sh[j * ld + i] = (-1.0 / sh[i * ld + i].r) * vv;
     }
-    __syncthreads();
-    // T^{-1} of this aggregate for the update kernel (zero on failure)
-    cx<double>* To = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
-    for (int e = l; e < n * n; e += blockDim.x) To[e] = Ti[e / n][e % n];
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = l; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    Tg[e] = i < j ? sh[j * ld + i] : i == j ? mk(dg[i], 0.0) : mk(0.0, 0.0);
   }
 }
 
 // Wout <- Xin T^{-1} on the FP64 matrix cores (16x16x4 MFMA): per aggregate
 // W (rows = 16 consecutive sites of one component, columns = test vectors)
-// = X T^{-1}, T^{-1} (upper triangular, from the Gram kernel) in LDS, the rows of X loaded straight from memory (16
-// consecutive sites per lane group, coalesced).  The K loop runs over all 32
-// padded test vectors with clamped loads and zero factors, so all loads of a
-// tile are in flight together.  A wave finishes reading its row tile before
-// it writes it and no other wave touches those rows, so the update may run
-// in place.
-template <typename Tin>
+// = X T^{-1}, T^{-1} (upper triangular, from the Cholesky kernel) in LDS, the
+// rows of X loaded straight from memory (16 consecutive sites per lane
+// group, coalesced).  The K loop runs over NQ = ceil(ntv / 4) steps of 4 test
+// vectors, unrolled, with clamped loads and zero factors for the padding, so
+// all loads of a tile are in flight together.  Since T^{-1} is upper
+// triangular, the column tile 0..15 takes only the K steps below 16 and the
+// column tile 16..31 exists only for ntv > 16: the skipped products are
+// exact zeros.  A wave finishes reading its row tile before it writes it
+// and no other wave touches those rows, so the update may run in place.
+template <typename Tin, int NQ>
 __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* Wout, const cx<Tin>* Xin, Geom g,
                                                                     const cx<double>* Tinv) {
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV + 1];
@@ -228,9 +244,9 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* 
   for (int tile = w; tile < ntile; tile += QR_THREADS / 64) {
     const int c = tile / tiles_per_comp, s0 = (tile % tiles_per_comp) * 16;
     const int sa = min(s0 + i16, vb - 1);  // A operand: site of this lane's row (clamped)
-    cx<double> xa[MAX_NTV / 4];
+    cx<double> xa[NQ];
 #pragma unroll
-    for (int q = 0; q < MAX_NTV / 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int k = min(4 * q + k4, n - 1);
       xa[q] = cvt<double>(Xin[((size_t)k * 12 + 6 * h + c) * V + base + sa]);
     }
@@ -240,11 +256,13 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* 
 #pragma unroll
       for (int v = 0; v < 4; ++v) RR[tj][v] = II[tj][v] = RI[tj][v] = IR[tj][v] = 0.0;
 #pragma unroll
-    for (int q = 0; q < MAX_NTV / 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const double f = 4 * q + k4 < n ? 1.0 : 0.0;  // padded test vectors add nothing
       const double ar = f * xa[q].r, ai = f * xa[q].i;
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj) {
+        if (tj == 0 && q >= 4) continue;  // rows 16.. of T^{-1} vanish in columns 0..15
+        if (tj == 1 && NQ <= 4) continue;  // no columns 16..31
         const cx<double> b = Ti[4 * q + k4][16 * tj + i16];
         RR[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.r, RR[tj], 0, 0, 0);
         II[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.i, II[tj], 0, 0, 0);
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* 
     }
     // result row lane / 16 + 4 v (site), column lane % 16 (test vector)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < (NQ > 4 ? 2 : 1); ++tj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int srow = s0 + k4 + 4 * v, j = 16 * tj + i16;
@@ -302,14 +320,32 @@ __global__ void dequantize_basis_kernel(cx<T>* out, BasisView<S> bv, int V, int 
 
 }  // namespace
 
+namespace {
+// the update kernel for K = ceil(ntv / 4) steps (ntv <= 32 is validated)
+template <typename Tin, int NQ = 8>
+void launch_qr_update(cx<double>* W, const cx<Tin>* X, const Geom& g, const cx<double>* tws, hipStream_t st) {
+  if constexpr (NQ > 1) {
+    if ((g.ntv + 3) / 4 < NQ) {
+      launch_qr_update<Tin, NQ - 1>(W, X, g, tws, st);
+      return;
+    }
+  }
+  qr_update_mfma_kernel<Tin, NQ><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, X, g, tws);
+}
+}  // namespace
+
 template <typename Tin>
 void launch_aggregate_qr(cx<double>* W, const cx<Tin>* X, const Geom& g, int* status, cx<double>* tws,
                          hipStream_t st) {
   // CholQR2: pass 1 from X into W, pass 2 on W in place
-  qr_gram_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(X, g, status, tws);
-  qr_update_mfma_kernel<Tin><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, X, g, tws);
-  qr_gram_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, g, status, tws);
-  qr_update_mfma_kernel<double><<<2 * g.nblocks, QR_THREADS, 0, st>>>(W, W, g, tws);
+  const unsigned nagg = 2 * g.nblocks;
+  const size_t chol_lds = sizeof(cx<double>) * g.ntv * (g.ntv + 1);
+  qr_gram_kernel<Tin><<<nagg, QR_THREADS, 0, st>>>(X, g, tws);
+  qr_chol_kernel<<<nagg, 64, chol_lds, st>>>(tws, g, status);
+  launch_qr_update<Tin>(W, X, g, tws, st);
+  qr_gram_kernel<double><<<nagg, QR_THREADS, 0, st>>>(W, g, tws);
+  qr_chol_kernel<<<nagg, 64, chol_lds, st>>>(tws, g, status);
+  launch_qr_update<double>(W, W, g, tws, st);
 }
 template void launch_aggregate_qr<double>(cx<double>*, const cx<double>*, const Geom&, int*, cx<double>*,
                                           hipStream_t);

@@ -335,6 +335,26 @@ def test_import_tv_resumes_setup():
     assert rc == 0
 
 
+@pytest.mark.parametrize("ntv", [4, 6, 12, 16, 20, 24, 28, 32])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_aggregate_orthonormalisation(prec, ntv):
+    """Alg. 5 on the GPU (CholQR2 behind ddamg_import_tv) against the
+    oracle's modified Gram-Schmidt of the same test vectors: every count of
+    4-vector K steps of the X T^-1 update (ntv up to 32), with and without
+    the second 16-column tile, on aggregates of 24 sites (ragged 16-site and
+    8-site tiles)."""
+    dd = _gpu()
+    L, block = (6, 4, 4, 4), (3, 2, 2, 2)
+    say("aggregate QR ntv", ntv, "prec", prec)
+    ctx, U = make_ctx(dd, L, block, 0.5, -0.2, ntv, prec)
+    tv = synth.gaussian_spinors(L, ntv, 90 + ntv)
+    ctx.import_tv(dev(tv))
+    W = torch.zeros_like(dev(tv))
+    ctx.export_basis(W)
+    ref = coarse.orthonormalise(sap.Blocking(L, block), tv)
+    assert rel(host(W), ref) <= {0: 1e-11, 1: 1e-5, 2: 1e-2}[prec]
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_import_coarse_injection(prec):
     """A D_c injected with ddamg_import_coarse (the oracle's) is the one

@@ -63,29 +63,29 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
   for (int t = 0; t < 6; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
   // Rows (site, spin-colour) of QR_CS sites at a time are staged in LDS with
   // coalesced loads (QR_CS consecutive sites of one test vector and
-  // component); the next chunk's loads are in flight while the MFMAs consume
-  // the current one.  Padded test vectors (a >= ntv) are not loaded.
+  // component); the loads of the next two chunks are in flight, held in the
+  // input precision, while the MFMAs consume the current one.  Padded test
+  // vectors (a >= ntv) are not loaded.
   constexpr int NQ = QR_ROWS * 32 / 256;
-  cx<double> xq[NQ];
-  auto fetch = [&](int s0) {
+  cx<Tin> xq0[NQ], xq1[NQ];
+  auto fetch = [&](cx<Tin>(&xq)[NQ], int s0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = l + 256 * q;
       const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
       const int sx = min(s0 + sl, vb - 1);
-      xq[q] = a < n ? cvt<double>(W[((size_t)a * 12 + 6 * h + c) * V + base + sx]) : mk(0.0, 0.0);
+      xq[q] = a < n ? W[((size_t)a * 12 + 6 * h + c) * V + base + sx] : mk((Tin)0, (Tin)0);
     }
   };
-  fetch(0);
-  for (int s0 = 0; s0 < vb; s0 += QR_CS) {
+  auto chunk = [&](cx<Tin>(&xq)[NQ], int s0) {
     __syncthreads();  // the previous chunk has been consumed
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = l + 256 * q;
       const int sl = e % QR_CS, rest = e / QR_CS, c = rest % 6, a = rest / 6;
-      Xs[sl * 6 + c][a] = s0 + sl < vb ? xq[q] : mk(0.0, 0.0);
+      Xs[sl * 6 + c][a] = s0 + sl < vb ? cvt<double>(xq[q]) : mk(0.0, 0.0);
     }
-    if (s0 + QR_CS < vb) fetch(s0 + QR_CS);
+    if (s0 + 2 * QR_CS < vb) fetch(xq, s0 + 2 * QR_CS);
     __syncthreads();
     // 4-row slices; the two products feeding one accumulator are issued
     // apart so no MFMA waits on the one before it
@@ -112,6 +112,12 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
         acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
       }
     }
+  };
+  fetch(xq0, 0);
+  if (QR_CS < vb) fetch(xq1, QR_CS);
+  for (int s0 = 0; s0 < vb; s0 += 2 * QR_CS) {
+    chunk(xq0, s0);
+    if (s0 + QR_CS < vb) chunk(xq1, s0 + QR_CS);
   }
   __syncthreads();  // the staging buffer is reused for the partial tiles
   // sum the four waves' tiles: waves 2,3 hand theirs to waves 0,1, then wave 1
@@ -231,25 +237,36 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* 
   const size_t V = g.V;
   const int vb = g.vblock;
   const int l = threadIdx.x, lane = l & 63, w = l >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const size_t base = (size_t)ci * vb;
+  const int tiles_per_comp = (vb + 15) / 16;
+  const int ntile = 6 * tiles_per_comp;
+  // the X rows of this wave's next tile, loaded (in the input precision)
+  // while the current tile is multiplied and stored; the rows of different
+  // tiles are disjoint, so this holds in place too
+  cx<Tin> xr[NQ];
+  auto fetch = [&](int tile) {
+    const int c = tile / tiles_per_comp, s0 = (tile % tiles_per_comp) * 16;
+    const int sa = min(s0 + i16, vb - 1);  // A operand: site of this lane's row (clamped)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = min(4 * q + k4, n - 1);
+      xr[q] = Xin[((size_t)k * 12 + 6 * h + c) * V + base + sa];
+    }
+  };
+  if (w < ntile) fetch(w);
   const cx<double>* Tg = Tinv + (size_t)blockIdx.x * MAX_NTV * MAX_NTV;
   for (int e = l; e < MAX_NTV * MAX_NTV; e += blockDim.x) {
     const int i = e / MAX_NTV, j = e % MAX_NTV;
     Ti[i][j] = (i < n && j < n) ? Tg[i * n + j] : mk(0.0, 0.0);
   }
   __syncthreads();
-  const int i16 = lane & 15, k4 = lane >> 4;
-  const size_t base = (size_t)ci * vb;
-  const int tiles_per_comp = (vb + 15) / 16;
-  const int ntile = 6 * tiles_per_comp;
   for (int tile = w; tile < ntile; tile += QR_THREADS / 64) {
     const int c = tile / tiles_per_comp, s0 = (tile % tiles_per_comp) * 16;
-    const int sa = min(s0 + i16, vb - 1);  // A operand: site of this lane's row (clamped)
     cx<double> xa[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int k = min(4 * q + k4, n - 1);
-      xa[q] = cvt<double>(Xin[((size_t)k * 12 + 6 * h + c) * V + base + sa]);
-    }
+    for (int q = 0; q < NQ; ++q) xa[q] = cvt<double>(xr[q]);
+    if (tile + QR_THREADS / 64 < ntile) fetch(tile + QR_THREADS / 64);
     qr_v4d RR[2], II[2], RI[2], IR[2];
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)

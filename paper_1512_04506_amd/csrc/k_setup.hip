@@ -225,12 +225,17 @@ __global__ __launch_bounds__(64) void qr_chol_kernel(cx<double>* tws, Geom g, in
 // all loads of a tile are in flight together.  Since T^{-1} is upper
 // triangular, the column tile 0..15 takes only the K steps below 16 and the
 // column tile 16..31 exists only for ntv > 16: the skipped products are
-// exact zeros.  A wave finishes reading its row tile before it writes it
-// and no other wave touches those rows, so the update may run in place.
+// exact zeros.  The result tile is transposed through the wave's own LDS
+// tile so that each store writes 16 consecutive sites (256 bytes) of 4 test
+// vectors.  A wave finishes reading its row tile before it writes it and no
+// other wave touches those rows, so the update may run in place.  Waves may
+// run different numbers of tiles, so the LDS exchange is ordered by
+// wave-scope fences, not workgroup barriers.
 template <typename Tin, int NQ>
 __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* Wout, const cx<Tin>* Xin, Geom g,
                                                                     const cx<double>* Tinv) {
   __shared__ cx<double> Ti[MAX_NTV][MAX_NTV + 1];
+  __shared__ cx<double> Sw[QR_THREADS / 64][MAX_NTV * 17];
   const int ci = blockIdx.x >> 1;
   const int h = blockIdx.x & 1;
   const int n = g.ntv;
@@ -287,15 +292,25 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* 
         IR[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.r, IR[tj], 0, 0, 0);
       }
     }
-    // result row lane / 16 + 4 v (site), column lane % 16 (test vector)
+    // result row lane / 16 + 4 v (site), column lane % 16 (test vector):
+    // transposed through this wave's LDS tile [column][site] (stride 17)
+    cx<double>* St = Sw[w];
 #pragma unroll
     for (int tj = 0; tj < (NQ > 4 ? 2 : 1); ++tj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int srow = s0 + k4 + 4 * v, j = 16 * tj + i16;
-        if (srow < vb && j < n)
-          Wout[((size_t)j * 12 + 6 * h + c) * V + base + srow] = mk(RR[tj][v] - II[tj][v], RI[tj][v] + IR[tj][v]);
-      }
+      for (int v = 0; v < 4; ++v)
+        St[(16 * tj + i16) * 17 + k4 + 4 * v] = mk(RR[tj][v] - II[tj][v], RI[tj][v] + IR[tj][v]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < (NQ > 4 ? 8 : 4); ++r) {
+      const int j = 4 * r + k4, srow = s0 + i16;
+      if (srow < vb && j < n) Wout[((size_t)j * 12 + 6 * h + c) * V + base + srow] = St[j * 17 + i16];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 

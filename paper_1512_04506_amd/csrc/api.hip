@@ -510,18 +510,21 @@ struct Solver final : SolverBase {
   // D_c = R D P from the stored basis, fill backward couplings by Eq. dagger,
   // quantise, and invert the even self blocks.
   void build_coarse_from(cx<double>* Wd) {
-    launch_quantize_basis<S>(Wq.get<stc_t<S>>(), Wsc.get<float>(), Wd, g, st);
-    const size_t nc = g.nc, nn = nc * nc;
     ensure_setup_ws();
-    cx<T>* D = ws_D.get<cx<T>>();
-    HIPCK(hipMemsetAsync(D, 0, sizeof(cx<T>) * g.nblocks * 9 * nn, st));
+    const size_t nc = g.nc, nn = nc * nc;
+    // the block pass reads the stored basis in T: for FP16 storage the FP32
+    // values scale * half, written by the quantisation itself
     const cx<T>* Wtp;
     if constexpr (is_half<S>()) {
-      launch_dequantize_basis<T, S>(ws_Wt.get<cx<T>>(), bv(), g, st);
+      static_assert(std::is_same<T, float>::value, "FP16 basis storage goes with FP32 arithmetic");
+      launch_quantize_basis<S>(Wq.get<stc_t<S>>(), Wsc.get<float>(), Wd, g, st, ws_Wt.get<cx<float>>());
       Wtp = ws_Wt.get<cx<T>>();
     } else {
+      launch_quantize_basis<S>(Wq.get<stc_t<S>>(), Wsc.get<float>(), Wd, g, st);
       Wtp = reinterpret_cast<const cx<T>*>(Wq.get<stc_t<S>>());
     }
+    cx<T>* D = ws_D.get<cx<T>>();
+    HIPCK(hipMemsetAsync(D, 0, sizeof(cx<T>) * g.nblocks * 9 * nn, st));
     // self slot: per chirality the block operator applied to all N_tv basis
     // columns, restricted; forward crossing slots: one fused contraction of
     // the basis (ntv <= 32 is validated at creation); backward slots by

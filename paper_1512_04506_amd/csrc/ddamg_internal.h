@@ -290,15 +290,20 @@ void launch_block_matvec(cx<T>* out, size_t ostr, const cx<T>* M, const cx<T>* x
                          int nrhs, hipStream_t st);
 
 // setup kernels
-// tws: workspace of 2 nblocks * QR_TWS_PER_AGG complex doubles (T^{-1} per aggregate)
+// tws: workspace of 2 nblocks * QR_TWS_PER_AGG complex doubles (per aggregate the
+// Gram matrix, then T^{-1})
 constexpr int QR_TWS_PER_AGG = 32 * 32;
 // Orthonormalises the test vectors X (precision Tin) on every aggregate into
 // the FP64 basis W (CholQR2; status set to 1 for a rank-deficient aggregate)
 template <typename Tin>
 void launch_aggregate_qr(cx<double>* W, const cx<Tin>* X, const Geom& g, int* status, cx<double>* tws,
                          hipStream_t st);
+// Stores the FP64 basis W in precision S (FP16 with a per-(vector, site)
+// scale in Wsc); for FP16, Wt (if given) receives the dequantised FP32
+// values scale * half, the same numbers launch_dequantize_basis produces
 template <typename S>
-void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st);
+void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st,
+                           cx<float>* Wt = nullptr);
 template <typename T, typename S>
 void launch_dequantize_basis(cx<T>* out, const BasisView<S>& bv, const Geom& g, hipStream_t st);
 template <typename T>

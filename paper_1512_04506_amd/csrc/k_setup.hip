@@ -315,7 +315,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_update_mfma_kernel(cx<double>* 
 }
 
 template <typename S>
-__global__ void quantize_basis_kernel(stc_t<S>* Wq, float* Wsc, const cx<double>* W, int V, int ntv) {
+__global__ void quantize_basis_kernel(stc_t<S>* Wq, float* Wsc, const cx<double>* W, int V, int ntv, cx<float>* Wt) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)ntv * V) return;
   const int s = (int)(idx % V);
@@ -332,8 +332,14 @@ __global__ void quantize_basis_kernel(stc_t<S>* Wq, float* Wsc, const cx<double>
     Wsc[idx] = fm;
     const double inv = fm > 0.f ? 1.0 / (double)fm : 0.0;
 #pragma unroll
-    for (int k = 0; k < 12; ++k)
-      Wq[((size_t)a * 12 + k) * V + s] = __floats2half2_rn((float)(v[k].r * inv), (float)(v[k].i * inv));
+    for (int k = 0; k < 12; ++k) {
+      const __half2 hq = __floats2half2_rn((float)(v[k].r * inv), (float)(v[k].i * inv));
+      Wq[((size_t)a * 12 + k) * V + s] = hq;
+      if (Wt) {
+        const float2 f = __half22float2(hq);
+        Wt[((size_t)a * 12 + k) * V + s] = mk(fm * f.x, fm * f.y);
+      }
+    }
   } else {
     for (int k = 0; k < 12; ++k) stc_store(Wq, ((size_t)a * 12 + k) * V + s, W[((size_t)a * 12 + k) * V + s]);
   }
@@ -384,9 +390,10 @@ template void launch_aggregate_qr<double>(cx<double>*, const cx<double>*, const 
 template void launch_aggregate_qr<float>(cx<double>*, const cx<float>*, const Geom&, int*, cx<double>*, hipStream_t);
 
 template <typename S>
-void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st) {
+void launch_quantize_basis(stc_t<S>* Wq, float* Wsc, const cx<double>* W, const Geom& g, hipStream_t st,
+                           cx<float>* Wt) {
   size_t n = (size_t)g.ntv * g.V;
-  quantize_basis_kernel<S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(Wq, Wsc, W, g.V, g.ntv);
+  quantize_basis_kernel<S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(Wq, Wsc, W, g.V, g.ntv, Wt);
 }
 template <typename T, typename S>
 void launch_dequantize_basis(cx<T>* out, const BasisView<S>& bv, const Geom& g, hipStream_t st) {
@@ -394,9 +401,12 @@ void launch_dequantize_basis(cx<T>* out, const BasisView<S>& bv, const Geom& g, 
   dequantize_basis_kernel<T, S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, bv, g.V, g.ntv);
 }
 
-template void launch_quantize_basis<double>(stc_t<double>*, float*, const cx<double>*, const Geom&, hipStream_t);
-template void launch_quantize_basis<float>(stc_t<float>*, float*, const cx<double>*, const Geom&, hipStream_t);
-template void launch_quantize_basis<__half>(stc_t<__half>*, float*, const cx<double>*, const Geom&, hipStream_t);
+template void launch_quantize_basis<double>(stc_t<double>*, float*, const cx<double>*, const Geom&, hipStream_t,
+                                            cx<float>*);
+template void launch_quantize_basis<float>(stc_t<float>*, float*, const cx<double>*, const Geom&, hipStream_t,
+                                            cx<float>*);
+template void launch_quantize_basis<__half>(stc_t<__half>*, float*, const cx<double>*, const Geom&, hipStream_t,
+                                            cx<float>*);
 template void launch_dequantize_basis<double, double>(cx<double>*, const BasisView<double>&, const Geom&, hipStream_t);
 template void launch_dequantize_basis<float, float>(cx<float>*, const BasisView<float>&, const Geom&, hipStream_t);
 template void launch_dequantize_basis<float, __half>(cx<float>*, const BasisView<__half>&, const Geom&, hipStream_t);

@@ -38,16 +38,24 @@ constexpr int QR_LD = MAX_NTV + 1;   // padded LDS row
 //              vectors (in place for the second pass).
 typedef double qr_v4d __attribute__((ext_vector_type(4)));
 
-template <typename Tin>
+// Column layouts of the Gram tiles (upper triangle of G = X^H X, 16x16
+// tiles, one lane per column in each operand):
+//   NT = 1, ntv <= 16: columns 0..15 x 0..15;
+//   NT = 2, ntv <= 24: columns 0..15 x 8..23 and {0..7, 16..23} x {0..7,
+//          16..23}: with columns in groups of eight, two tiles hold every
+//          pair i <= j (the pairs 0..7 x 16..23 of the second are dropped);
+//   NT = 3, ntv <= 32: 0..15 x 0..15, 0..15 x 16..31 and 16..31 x 16..31.
+template <typename Tin, int NT>
 __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, Geom g, cx<double>* Gout) {
+  constexpr int NACC = 2 * NT;  // Re and Im of each tile
   // the staged rows of the Gram matrix pass, later the partial tiles of two
   // waves
-  constexpr size_t STAGE_BYTES = sizeof(cx<double>) * QR_ROWS * QR_LD > sizeof(qr_v4d) * 2 * 6 * 64
+  constexpr size_t STAGE_BYTES = sizeof(cx<double>) * QR_ROWS * QR_LD > sizeof(qr_v4d) * 2 * NACC * 64
                                      ? sizeof(cx<double>) * QR_ROWS * QR_LD
-                                     : sizeof(qr_v4d) * 2 * 6 * 64;
+                                     : sizeof(qr_v4d) * 2 * NACC * 64;
   __shared__ __attribute__((aligned(32))) char stage_raw[STAGE_BYTES];
   auto Xs = reinterpret_cast<cx<double>(*)[QR_LD]>(stage_raw);
-  auto part = reinterpret_cast<qr_v4d(*)[6][64]>(stage_raw);
+  auto part = reinterpret_cast<qr_v4d(*)[NACC][64]>(stage_raw);
   const int ci = blockIdx.x >> 1;  // internal block: its sites are ci * vblock + [0, vblock)
   const int h = blockIdx.x & 1;
   const int n = g.ntv;
@@ -55,12 +63,15 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
   const int vb = g.vblock;
   const int l = threadIdx.x, lane = l & 63, w = l >> 6;
   const size_t base = (size_t)ci * vb;
-  const bool two = n > 16;  // second column tile (columns 16..31)
   const int col0 = lane & 15, rsub = lane >> 4;
-  // tiles: 0 = Re(0,0) 1 = Im(0,0) 2 = Re(0,1) 3 = Im(0,1) 4 = Re(1,1) 5 = Im(1,1)
-  qr_v4d acc[6];
+  // operand columns of this lane: ca (first operand of tile 0), cb (second
+  // operand of tile 0), cc (both operands of the last tile)
+  const int ca = col0;
+  const int cb = NT == 2 ? 8 + col0 : col0;
+  const int cc = NT == 2 ? (col0 < 8 ? col0 : col0 + 8) : 16 + col0;
+  qr_v4d acc[NACC];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NACC; ++t) acc[t] = (qr_v4d){0.0, 0.0, 0.0, 0.0};
   // Rows (site, spin-colour) of QR_CS sites at a time are staged in LDS with
   // coalesced loads (QR_CS consecutive sites of one test vector and
   // component); the loads of the next two chunks are in flight, held in the
@@ -90,9 +101,25 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
     // 4-row slices; the two products feeding one accumulator are issued
     // apart so no MFMA waits on the one before it
     for (int t = w; t < QR_ROWS / 4; t += 4) {
-      const cx<double> y0 = Xs[4 * t + rsub][col0];
-      if (two) {
-        const cx<double> y1 = Xs[4 * t + rsub][16 + col0];
+      const cx<double> y0 = Xs[4 * t + rsub][ca];
+      if constexpr (NT == 1) {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
+      } else if constexpr (NT == 2) {
+        const cx<double> yb = Xs[4 * t + rsub][cb];
+        const cx<double> yc = Xs[4 * t + rsub][cc];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, yb.r, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, yb.i, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(yc.r, yc.r, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(yc.r, yc.i, acc[3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, yb.i, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, yb.r, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(yc.i, yc.i, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-yc.i, yc.r, acc[3], 0, 0, 0);
+      } else {
+        const cx<double> y1 = Xs[4 * t + rsub][cc];
         acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
         acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y1.r, acc[2], 0, 0, 0);
@@ -105,11 +132,6 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
         acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y1.r, acc[3], 0, 0, 0);
         acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1.i, y1.i, acc[4], 0, 0, 0);
         acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1.i, y1.r, acc[5], 0, 0, 0);
-      } else {
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.r, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.r, y0.i, acc[1], 0, 0, 0);
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0.i, y0.i, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y0.i, y0.r, acc[1], 0, 0, 0);
       }
     }
   };
@@ -121,28 +143,38 @@ __global__ __launch_bounds__(QR_THREADS) void qr_gram_kernel(const cx<Tin>* W, G
   }
   __syncthreads();  // the staging buffer is reused for the partial tiles
   // sum the four waves' tiles: waves 2,3 hand theirs to waves 0,1, then wave 1
-  // to wave 0, which writes the upper tiles of G (row-major, stride MAX_NTV)
+  // to wave 0, which writes the upper triangle of G (row-major, stride
+  // MAX_NTV)
   if (w >= 2)
 #pragma unroll
-    for (int t = 0; t < 6; ++t) part[w - 2][t][lane] = acc[t];
+    for (int t = 0; t < NACC; ++t) part[w - 2][t][lane] = acc[t];
   __syncthreads();
   if (w < 2)
 #pragma unroll
-    for (int t = 0; t < 6; ++t) acc[t] += part[w][t][lane];
+    for (int t = 0; t < NACC; ++t) acc[t] += part[w][t][lane];
   __syncthreads();
   if (w == 1)
 #pragma unroll
-    for (int t = 0; t < 6; ++t) part[0][t][lane] = acc[t];
+    for (int t = 0; t < NACC; ++t) part[0][t][lane] = acc[t];
   __syncthreads();
   if (w == 0) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) acc[t] += part[0][t][lane];
+    for (int t = 0; t < NACC; ++t) acc[t] += part[0][t][lane];
     cx<double>* G = Gout + (size_t)blockIdx.x * QR_TWS_PER_AGG;
+    // f64 16x16x4 result v of lane l: row l/16 + 4v (first operand's
+    // column), column l%16 (second operand's column)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = rsub + 4 * v, j = col0;  // f64 16x16x4 result: row l/16 + 4v, column l%16
-      if (i < n && j < n) G[i * MAX_NTV + j] = mk(acc[0][v], acc[1][v]);
-      if (two) {
+      const int i = rsub + 4 * v, j = col0;
+      if constexpr (NT == 1) {
+        if (i < n && j < n) G[i * MAX_NTV + j] = mk(acc[0][v], acc[1][v]);
+      } else if constexpr (NT == 2) {
+        const int ib = 8 + j;  // tile 0: rows 0..15, columns 8..23
+        if (i <= ib && ib < n) G[i * MAX_NTV + ib] = mk(acc[0][v], acc[1][v]);
+        const int ic = i < 8 ? i : i + 8, jc = j < 8 ? j : j + 8;  // tile 1
+        if (ic <= jc && jc < n && !(ic < 8 && jc >= 16)) G[ic * MAX_NTV + jc] = mk(acc[2][v], acc[3][v]);
+      } else {
+        if (i < n && j < n) G[i * MAX_NTV + j] = mk(acc[0][v], acc[1][v]);
         if (i < n && 16 + j < n) G[i * MAX_NTV + 16 + j] = mk(acc[2][v], acc[3][v]);
         if (16 + i < n && 16 + j < n) G[(16 + i) * MAX_NTV + 16 + j] = mk(acc[4][v], acc[5][v]);
       }
@@ -359,6 +391,17 @@ __global__ void dequantize_basis_kernel(cx<T>* out, BasisView<S> bv, int V, int 
 }  // namespace
 
 namespace {
+// the Gram kernel with the fewest column tiles for ntv (ntv <= 32 is validated)
+template <typename Tin>
+void launch_qr_gram(const cx<Tin>* X, const Geom& g, cx<double>* tws, hipStream_t st) {
+  const unsigned nagg = 2 * g.nblocks;
+  if (g.ntv <= 16)
+    qr_gram_kernel<Tin, 1><<<nagg, QR_THREADS, 0, st>>>(X, g, tws);
+  else if (g.ntv <= 24)
+    qr_gram_kernel<Tin, 2><<<nagg, QR_THREADS, 0, st>>>(X, g, tws);
+  else
+    qr_gram_kernel<Tin, 3><<<nagg, QR_THREADS, 0, st>>>(X, g, tws);
+}
 // the update kernel for K = ceil(ntv / 4) steps (ntv <= 32 is validated)
 template <typename Tin, int NQ = 8>
 void launch_qr_update(cx<double>* W, const cx<Tin>* X, const Geom& g, const cx<double>* tws, hipStream_t st) {
@@ -378,10 +421,10 @@ void launch_aggregate_qr(cx<double>* W, const cx<Tin>* X, const Geom& g, int* st
   // CholQR2: pass 1 from X into W, pass 2 on W in place
   const unsigned nagg = 2 * g.nblocks;
   const size_t chol_lds = sizeof(cx<double>) * g.ntv * (g.ntv + 1);
-  qr_gram_kernel<Tin><<<nagg, QR_THREADS, 0, st>>>(X, g, tws);
+  launch_qr_gram<Tin>(X, g, tws, st);
   qr_chol_kernel<<<nagg, 64, chol_lds, st>>>(tws, g, status);
   launch_qr_update<Tin>(W, X, g, tws, st);
-  qr_gram_kernel<double><<<nagg, QR_THREADS, 0, st>>>(W, g, tws);
+  launch_qr_gram<double>(W, g, tws, st);
   qr_chol_kernel<<<nagg, 64, chol_lds, st>>>(tws, g, status);
   launch_qr_update<double>(W, W, g, tws, st);
 }

@@ -388,9 +388,6 @@ __global__ void dequantize_basis_kernel(cx<T>* out, BasisView<S> bv, int V, int 
   out[idx] = sc * ldc<T>(bv.W, idx);
 }
 
-}  // namespace
-
-namespace {
 // the Gram kernel with the fewest column tiles for ntv (ntv <= 32 is validated)
 template <typename Tin>
 void launch_qr_gram(const cx<Tin>* X, const Geom& g, cx<double>* tws, hipStream_t st) {

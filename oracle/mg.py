@@ -16,8 +16,10 @@
              at the end.
 
 Parity status: vcycle, fgmres and the pieces of setup are pinned by the
-tests; the composition of setup (the order of its passes) has no external
-pin and is "parity unpinned" beyond the span and orthonormality checks.
+tests; the composition of setup (the number and order of its passes) is
+pinned on a gauge field with the links across block faces cut, where every
+smoother pass and V-cycle is an exact D^{-1} and Alg. 4 has the closed form
+V ~ D^{-(3 + N_setup)} V_0 (dense solves).
 """
 import numpy as np
 

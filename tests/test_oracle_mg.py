@@ -96,3 +96,34 @@ def test_solve_with_point_sources_and_restart():
     u, st = M.solve(f)
     assert mg.true_relres(M.D, u, f) <= 1e-10
     assert st['restarts'] >= 2
+
+
+def test_setup_composition_with_decoupled_blocks():
+    """Pin of the order of Alg. 4's passes.  With the links across block faces
+    cut, D is block diagonal; with the block MR run to convergence every SAP
+    cycle returns the block solve, so each smoother pass from zero and each
+    V-cycle (whatever the coarse correction gave as start) returns D^{-1} y.
+    Alg. 4 then leaves every test vector along D^{-(3 + N_setup)} v for its
+    start vector v (three smoother passes, N_setup V-cycle passes), unit
+    normalised, and the basis is their aggregate Gram-Schmidt.  A pass too
+    many or too few changes the power and fails the check."""
+    Ls, bs, ntv, n_setup = (4, 4, 2, 2), (2, 2, 1, 1), 4, 2
+    U = synth.su3_field(Ls, 0.5, 61)
+    c = dirac.coords(Ls)
+    for mu in range(4):
+        U[..., mu, :, :][(c[mu] % bs[mu]) == bs[mu] - 1] = 0.0
+    p = mg.Params(Ls, bs, -0.2, 1.0, ntv, n_setup=n_setup, n_mr=80)
+    M = mg.MG(p, U)
+    v0 = synth.gaussian_spinors(Ls, ntv, 62)
+    V = M.setup(v0)
+    shp = (Ls[3], Ls[2], Ls[1], Ls[0], 4, 3)
+    D = dense_from_apply(M.D, shp)
+    for j in range(ntv):
+        x = v0[j].reshape(-1)
+        for _ in range(3 + n_setup):
+            x = np.linalg.solve(D, x)
+        x /= np.linalg.norm(x)
+        assert relerr(V[j].reshape(-1), x) < 1e-9
+        # one power fewer is far off (the check has teeth)
+        assert relerr(V[j].reshape(-1), D @ x / np.linalg.norm(D @ x)) > 1e-3
+    assert relerr(M.W, coarse.orthonormalise(M.blk, V)) < 1e-12

@@ -418,3 +418,37 @@ def test_allocator_hook_owns_workspace():
     A = dirac.clover_term(U, m0, 1.0)
     res = f[0] - dirac.apply_D(U, A, host(u)[0])
     assert np.linalg.norm(res) / np.linalg.norm(f[0]) <= 1e-10
+
+
+def test_kernel_timing_counts():
+    """ddamg_set_kernel_timing / ddamg_get_kernel_times (what the benchmark's
+    roofline reads): one outer Gram-Schmidt group and one w = D z per outer
+    iteration with all rhs, one aggregate QR per basis build (1 + N_setup
+    builds of N_tv vectors), positive times; enabling zeroes the sums and
+    nothing is counted while timing is off."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    say("kernel timing")
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 2)
+    n_setup = ctx.params.n_setup
+    ctx.set_kernel_timing(True)
+    ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 91)))
+    f = synth.gaussian_spinors(L, 2, 92)
+    u = torch.zeros_like(dev(f))
+    rc, st = ctx.solve(u, dev(f), 2, 1e-10)
+    assert rc == 0
+    kt = ctx.kernel_times()
+    its = st["outer_iterations"]
+    assert kt["outer_gs"][1:] == (its, 2 * its)
+    assert kt["dslash"][1:] == (its, 2 * its)
+    assert kt["setup_qr"][1:] == (1 + n_setup, (1 + n_setup) * ntv)
+    for k in ("sap", "restrict", "prolong", "coarse", "outer_gs", "setup_qr", "setup_galerkin"):
+        assert kt[k][0] > 0.0 and kt[k][1] > 0, (k, kt[k])
+    ctx.set_kernel_timing(True)
+    assert all(v == (0.0, 0, 0) for v in ctx.kernel_times().values())
+    ctx.set_kernel_timing(False)
+    u.zero_()
+    rc, st = ctx.solve(u, dev(f), 2, 1e-10)
+    assert rc == 0
+    assert all(v == (0.0, 0, 0) for v in ctx.kernel_times().values())
+    ctx.close()

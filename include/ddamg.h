@@ -222,8 +222,14 @@ int ddamg_reset_stats(ddamg_ctx* ctx);
  * Spinor fields in the library's internal layout: site-major
  * structure-of-arrays complex, element (rhs, comp, site) at
  * (rhs * 12 + comp) * V + site, comp = 3 spin + colour, complex128 for
- * DDAMG_FP64 and complex64 for DDAMG_FP32 / DDAMG_MIXED16.  No layout
- * conversion is performed; out != in; asynchronous. */
+ * DDAMG_FP64 and complex64 for DDAMG_FP32 / DDAMG_MIXED16.  Internal site
+ * order (block-major): the site with coordinates x = block * bc + lc has
+ * index ci * V_block + l, where l = lc_x + b_x (lc_y + b_y (lc_z + b_z lc_t))
+ * is its place in the block (b = block extents), lexb the lexicographic
+ * block index of bc (as for coarse fields above) and
+ * ci = ((bc_x + bc_y + bc_z + bc_t) mod 2) * Nblock / 2 + lexb / 2 (integer
+ * division): even blocks first.  No layout conversion is performed;
+ * out != in; asynchronous. */
 int dirac_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
 
 /* Coarse fields in the internal layout of the context's arithmetic

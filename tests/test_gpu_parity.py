@@ -452,3 +452,61 @@ def test_kernel_timing_counts():
     assert rc == 0
     assert all(v == (0.0, 0, 0) for v in ctx.kernel_times().values())
     ctx.close()
+
+
+def _internal_site_index(L, block):
+    """Internal (block-major) site index of every canonical site, in the
+    canonical order [t][z][y][x], from the order stated in the header."""
+    NB = [L[m] // block[m] for m in range(4)]
+    t, z, y, x = np.meshgrid(*[np.arange(L[m]) for m in (3, 2, 1, 0)], indexing="ij")
+    c = [x, y, z, t]
+    bc = [c[m] // block[m] for m in range(4)]
+    lc = [c[m] % block[m] for m in range(4)]
+    l = lc[0] + block[0] * (lc[1] + block[1] * (lc[2] + block[2] * lc[3]))
+    lexb = bc[0] + NB[0] * (bc[1] + NB[1] * (bc[2] + NB[2] * bc[3]))
+    nb = NB[0] * NB[1] * NB[2] * NB[3]
+    ci = ((bc[0] + bc[1] + bc[2] + bc[3]) % 2) * (nb // 2) + lexb // 2
+    vb = block[0] * block[1] * block[2] * block[3]
+    return (ci * vb + l).reshape(-1), ci, lexb
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_internal_layout_applies(prec):
+    """dirac_apply_internal and coarse_apply_internal on fields permuted into
+    the internal order the header states match the oracle's D and D_c."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["ragged_6x4x4x4"]
+    say("internal applies prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec)
+    A = dirac.clover_term(U, m0, 1.0)
+    V = int(np.prod(L))
+    S, _, _ = _internal_site_index(L, block)
+    assert np.array_equal(np.sort(S), np.arange(V))
+    ct = np.complex128 if prec == 0 else np.complex64
+    psi = synth.gaussian_spinors(L, 2, 95)
+    inner = np.zeros((2, 12, V), dtype=ct)
+    inner[:, :, S] = psi.reshape(2, V, 12).transpose(0, 2, 1)
+    out = torch.zeros_like(dev(inner))
+    ctx.dirac_apply_internal(out, dev(inner), 2, prec)
+    got = host(out)[:, :, S].transpose(0, 2, 1).reshape(psi.shape)
+    ref = np.stack([dirac.apply_D(U, A, psi[r]) for r in range(2)])
+    assert rel(got, ref) <= TOL[prec]
+    # coarse fields: internal coarse site ci of every lexicographic block
+    blk, W = _basis(L, block, ntv)
+    ctx.import_basis(dev(W))
+    nb, n = blk.nblocks, 2 * ntv
+    Dc_ref = coarse.coarse_operator(U, A, blk, W)
+    NB = [L[m] // block[m] for m in range(4)]
+    bcs = np.array([[b % NB[0], (b // NB[0]) % NB[1], (b // (NB[0] * NB[1])) % NB[2], b // (NB[0] * NB[1] * NB[2])]
+                    for b in range(nb)])
+    cib = (bcs.sum(axis=1) % 2) * (nb // 2) + np.arange(nb) // 2
+    assert np.array_equal(np.sort(cib), np.arange(nb))
+    xc = synth.gaussian_coarse(nb, ntv, 2, 96).reshape(2, nb, n)
+    cin = np.zeros((2, nb, n), dtype=ct)
+    cin[:, cib, :] = xc
+    cout = torch.zeros_like(dev(cin))
+    ctx.coarse_apply_internal(cout, dev(cin), 2)
+    gotc = host(cout)[:, cib, :]
+    refc = coarse.coarse_apply(Dc_ref, coarse.neighbour_table(blk), xc)
+    assert rel(gotc, refc) <= TOL[prec]
+    ctx.close()

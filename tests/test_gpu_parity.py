@@ -510,3 +510,37 @@ def test_internal_layout_applies(prec):
     refc = coarse.coarse_apply(Dc_ref, coarse.neighbour_table(blk), xc)
     assert rel(gotc, refc) <= TOL[prec]
     ctx.close()
+
+
+def test_rhs_count_rejected_before_any_work():
+    """Every multi-rhs entry point returns -1 (bad argument) for nrhs = 0 and
+    nrhs > max_rhs and leaves its output untouched (buffers are sized for
+    max_rhs + 1, so nothing could run out of bounds either way)."""
+    dd = _gpu()
+    import ctypes
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, 2)
+    blk, W = _basis(L, block, ntv)
+    ctx.import_basis(dev(W))
+    mr = ctx.params.max_rhs
+    fine = dev(synth.gaussian_spinors(L, mr + 1, 97))
+    crs = dev(synth.gaussian_coarse(blk.nblocks, ntv, mr + 1, 98))
+    fo, co = torch.full_like(fine, 7.0), torch.full_like(crs, 7.0)
+    fp, cp = ctypes.c_void_p(fine.data_ptr()), ctypes.c_void_p(crs.data_ptr())
+    fop, cop = ctypes.c_void_p(fo.data_ptr()), ctypes.c_void_p(co.data_ptr())
+    lib, h = dd.lib, ctx.h
+    for n in (0, mr + 1):
+        calls = {
+            "dirac_apply": lambda: lib.dirac_apply(h, fop, fp, n, dd.MIXED16),
+            "mg_apply": lambda: lib.mg_apply(h, fop, fp, n),
+            "coarse_apply": lambda: lib.coarse_apply(h, cop, cp, n),
+            "mg_restrict": lambda: lib.mg_restrict(h, cop, fp, n),
+            "mg_prolong": lambda: lib.mg_prolong(h, fop, cp, n),
+            "solve": lambda: lib.solve(h, fop, fp, n, 1e-10, ctypes.byref(dd.Stats())),
+        }
+        for name, call in calls.items():
+            assert call() == -1, (name, n)
+            assert b"nrhs" in lib.ddamg_last_error(h), name
+    torch.cuda.synchronize()
+    assert bool((fo == 7.0).all()) and bool((co == 7.0).all())
+    ctx.close()

@@ -41,6 +41,13 @@ inline void check_launch(const char* what) {
   if (e != hipSuccess) throw Fail{DDAMG_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+// A multi-dot launcher refuses (returns false, launches nothing) when its
+// partial-sum buffer is smaller than the call needs; that is a sizing error
+// of this library, reported instead of writing past the buffer.
+inline void need_part(bool launched, const char* what) {
+  if (!launched) throw Fail{DDAMG_ENOMEM, std::string(what) + ": partial-sum workspace too small"};
+}
+
 // Workspace allocator: hipMalloc / hipFree unless the caller installed a
 // hook; every buffer remembers the release function it was allocated with.
 ddamg_alloc_fn g_alloc = nullptr;
@@ -258,6 +265,7 @@ namespace {
 struct Krylov {
   DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, kdone, h1, h2, n2, part, wscale;
   int m = 0, maxr = 0, ldh = 0;
+  size_t part_cap = 0;  // entries of part
   ArnoldiState st{};
   void alloc(int m_, int maxr_, size_t n_per_rhs) {
     m = m_;
@@ -277,7 +285,8 @@ struct Krylov {
     h2.alloc<cx<double>>((size_t)maxr * ldh);
     n2.alloc<cx<double>>(maxr);
     wscale.alloc<double>(maxr);
-    part.alloc<cx<double>>((size_t)maxr * (m + 1) * blas_nchunks(n_per_rhs));
+    part_cap = krylov_part_entries(m, maxr, n_per_rhs);
+    part.alloc<cx<double>>(part_cap);
     st.H = H.get<cx<double>>();
     st.cs = cs.get<cx<double>>();
     st.sn = sn.get<cx<double>>();
@@ -319,6 +328,9 @@ struct Solver final : SolverBase {
   // coarse work vectors (T)
   DevBuf yc, xc, te, ue, bo, cw, cV;
   Krylov ck;
+  // partial sums of the setup's test-vector norms (fine vectors, ntv rhs)
+  DevBuf npart;
+  size_t npart_cap = 0;
   // outer FGMRES
   DevBuf oV, oZ, ow, of, ou, oyT;
   Krylov ok;
@@ -366,6 +378,8 @@ struct Solver final : SolverBase {
     const int mc = c->p.coarse_restart;
     cV.alloc<cx<T>>((size_t)(mc + 1) * maxr * osz());
     ck.alloc(mc, maxr, std::max(osz(), csz()));
+    npart_cap = setup_norm_part_entries(g.ntv, fsz());
+    npart.alloc<cx<double>>(npart_cap);
   }
 
   // ------------------------------------------------------------ smoother
@@ -408,13 +422,17 @@ struct Solver final : SolverBase {
   void cgs2(Krylov& K, Tv* Vb, size_t vsj, size_t vsr, int k, Tv* w, size_t wsr, size_t n, int nrhs) {
     using E = typename std::remove_cv<decltype(Vb->r)>::type;
     const int* act = K.active.get<int>();
-    launch_mdot<E>(K.h1.get<cx<double>>(), K.ldh, K.part.get<cx<double>>(), Vb, vsj, vsr, k + 1, w, wsr, n, nrhs, act,
-                   st);
+    cx<double>* part = K.part.get<cx<double>>();
+    need_part(launch_mdot<E>(K.h1.get<cx<double>>(), K.ldh, part, K.part_cap, Vb, vsj, vsr, k + 1, w, wsr, n, nrhs,
+                             act, st),
+              "coarse Gram-Schmidt");
     launch_maxpy<E, E>(w, wsr, Vb, vsj, vsr, k + 1, K.h1.get<cx<double>>(), K.ldh, -1.0, n, nrhs, act, st);
-    launch_mdot<E>(K.h2.get<cx<double>>(), K.ldh, K.part.get<cx<double>>(), Vb, vsj, vsr, k + 1, w, wsr, n, nrhs, act,
-                   st);
+    need_part(launch_mdot<E>(K.h2.get<cx<double>>(), K.ldh, part, K.part_cap, Vb, vsj, vsr, k + 1, w, wsr, n, nrhs,
+                             act, st),
+              "coarse Gram-Schmidt");
     launch_maxpy<E, E>(w, wsr, Vb, vsj, vsr, k + 1, K.h2.get<cx<double>>(), K.ldh, -1.0, n, nrhs, act, st);
-    launch_mdot<E>(K.n2.get<cx<double>>(), 1, K.part.get<cx<double>>(), w, 0, wsr, 1, w, wsr, n, nrhs, act, st);
+    need_part(launch_mdot<E>(K.n2.get<cx<double>>(), 1, part, K.part_cap, w, 0, wsr, 1, w, wsr, n, nrhs, act, st),
+              "coarse Gram-Schmidt");
   }
 
   // x_c = D_c^{-1} y_c approximately (Alg. 2), y_c/x_c full [nrhs][Nb][nc]
@@ -425,8 +443,9 @@ struct Solver final : SolverBase {
     const int m = c->p.coarse_restart;
     const int maxit = fixed > 0 ? fixed : c->p.coarse_maxit;
     // ||y_c|| per rhs -> absolute tolerance (computed on the device)
-    launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), ycv, 0, cs_, 1, ycv, cs_, cs_, nrhs, nullptr,
-                   st);
+    need_part(launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), ck.part_cap, ycv, 0, cs_, 1, ycv,
+                             cs_, cs_, nrhs, nullptr, st),
+              "coarse right-hand side norm");
     launch_set_abstol(ck.abstol.get<double>(), ck.n2.get<cx<double>>(), fixed > 0 ? -1.0 : c->p.coarse_tol, nrhs, st);
     // b_o = y_o - D_oe D_ee^{-1} y_e
     launch_block_matvec<T>(te.get<cx<T>>(), esz(), Dinv.get<cx<T>>(), ycv, cs_, g.neven, g.nc, nrhs, st);
@@ -447,8 +466,9 @@ struct Solver final : SolverBase {
         launch_sub<T>(Vb, vsr, bo.get<cx<T>>(), osz(), cw.get<cx<T>>(), osz(), osz(), nrhs, st);
       }
       first = false;
-      launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), Vb, 0, vsr, 1, Vb, vsr, osz(), nrhs,
-                     nullptr, st);
+      need_part(launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), ck.part_cap, Vb, 0, vsr, 1, Vb,
+                               vsr, osz(), nrhs, nullptr, st),
+                "coarse residual norm");
       launch_arnoldi_start(ck.st, ck.n2.get<cx<double>>(), 1, nrhs, st);
       launch_scale<T, T>(Vb, vsr, Vb, vsr, ck.inv_h.get<double>(), osz(), nrhs, nullptr, st);
       if (!read_any_active(ck, nrhs)) break;
@@ -494,8 +514,9 @@ struct Solver final : SolverBase {
 
   // ---------------------------------------------------------------- setup
   void normalise(cx<T>* v, int n) {
-    launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), v, 0, fsz(), 1, v, fsz(), fsz(), n, nullptr,
-                   st);
+    need_part(launch_mdot<T>(ck.n2.get<cx<double>>(), 1, npart.get<cx<double>>(), npart_cap, v, 0, fsz(), 1, v, fsz(),
+                             fsz(), n, nullptr, st),
+              "test-vector norms");
     HIPCK(hipMemsetAsync(c->status.get<int>(), 0, sizeof(int), st));
     launch_inv_norm(ck.inv_h.get<double>(), ck.n2.get<cx<double>>(), n, c->status.get<int>(), st);
     launch_scale<T, T>(v, fsz(), v, fsz(), ck.inv_h.get<double>(), fsz(), n, nullptr, st);
@@ -662,12 +683,6 @@ struct Solver final : SolverBase {
   }
 
   // ------------------------------------------------------- outer FGMRES
-  // Classical Gram-Schmidt of w = V_{k+1} against V_0..V_k with selective
-  // re-orthogonalisation: one multi-dot gives V^H w and |w|^2 together (w is
-  // the next basis slot), and a second pass runs only if some rhs lost more
-  // than half of |w|^2 in the projection (norm ratio below 1/sqrt 2), the
-  // criterion of Daniel, Gragg, Kaufman and Stewart.  Returns whether the
-  // second pass ran (its coefficients are then in h2).
   // Classical Gram-Schmidt done twice against the outer basis V_0..V_k:
   // h1 = V^H w; w <- w - V h1 and h2 = V^H w in one fused pass; the norm of
   // w'' = w - V h2 from |w|^2 - |h2|^2 (V orthonormal); w <- w'' / |w''| in
@@ -677,15 +692,19 @@ struct Solver final : SolverBase {
     const size_t n = fsz();
     const int* act = ok.active.get<int>();
     cx<double>* w = V + (size_t)(k + 1) * vsj;
-    launch_mdot<double>(ok.h1.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 1, w, n, n, nrhs,
-                        act, st);
+    cx<double>* part = ok.part.get<cx<double>>();
+    need_part(launch_mdot<double>(ok.h1.get<cx<double>>(), ok.ldh, part, ok.part_cap, V, vsj, n, k + 1, w, n, n, nrhs,
+                                  act, st),
+              "outer Gram-Schmidt");
     if (k + 1 <= GS_FUSED_MAXV) {
-      launch_gs_fused(ok.h2.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 1, w, n,
-                      ok.h1.get<cx<double>>(), n, nrhs, act, st);
+      need_part(launch_gs_fused(ok.h2.get<cx<double>>(), ok.ldh, part, ok.part_cap, V, vsj, n, k + 1, w, n,
+                                ok.h1.get<cx<double>>(), n, nrhs, act, st),
+                "outer Gram-Schmidt");
     } else {  // long cycles: the same step in two passes (the last vector is w itself: |w|^2)
       launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h1.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
-      launch_mdot<double>(ok.h2.get<cx<double>>(), ok.ldh, ok.part.get<cx<double>>(), V, vsj, n, k + 2, w, n, n,
-                          nrhs, act, st);
+      need_part(launch_mdot<double>(ok.h2.get<cx<double>>(), ok.ldh, part, ok.part_cap, V, vsj, n, k + 2, w, n, n,
+                                    nrhs, act, st),
+                "outer Gram-Schmidt");
     }
     launch_gs_norm(ok.n2.get<cx<double>>(), ok.wscale.get<double>(), ok.h2.get<cx<double>>(), ok.ldh, k + 1, nrhs,
                    act, st);
@@ -742,7 +761,9 @@ struct Solver final : SolverBase {
     launch_spinor_to_internal<double>(f, reinterpret_cast<const cx<double>*>(f_canon), g, nrhs, st);
     launch_spinor_to_internal<double>(u, reinterpret_cast<const cx<double>*>(u_canon), g, nrhs, st);
     // ||f||
-    launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), f, 0, n, 1, f, n, n, nrhs, nullptr, st);
+    need_part(launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), ok.part_cap, f, 0, n, 1, f, n,
+                                  n, nrhs, nullptr, st),
+              "right-hand side norm");
     std::vector<cx<double>> fn2(nrhs), rn2(nrhs);
     HIPCK(hipMemcpyAsync(c->h_cx, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost, st));
     c->sync();
@@ -771,8 +792,9 @@ struct Solver final : SolverBase {
       c->timed(DDAMG_KERNEL_RESIDUAL, nrhs,
                [&] { launch_dslash<double, double, double, double>(w, u, g64, g, nrhs, DS_FULL, 0, -1, n, n, st); });
       launch_sub<double>(V, n, f, n, w, n, n, nrhs, st);
-      launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), V, 0, n, 1, V, n, n, nrhs, nullptr,
-                          st);
+      need_part(launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), ok.part_cap, V, 0, n, 1, V,
+                                    n, n, nrhs, nullptr, st),
+                "residual norm");
       HIPCK(hipMemcpyAsync(c->h_cx, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost, st));
       c->sync();
       std::copy(c->h_cx, c->h_cx + nrhs, rn2.begin());

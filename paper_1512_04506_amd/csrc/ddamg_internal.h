@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "blas_sizes.h"
+
 namespace ddamg {
 
 // ---------------------------------------------------------------- complex
@@ -324,10 +326,12 @@ void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& 
 
 // BLAS on block vectors x[r * rstride + i], i < n, r < nrhs.
 // partial dots: part[(r * nvec + j) * nchunk + c]; final h[r * ldh + j].
-int blas_nchunks(size_t n);
+// The multi-dot launchers take the capacity of part in entries and return
+// false, launching nothing, if the call needs more (mdot_part_entries).
 template <typename T>
-void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size_t vstride_j, size_t vstride_r,
-                 int nvec, const cx<T>* w, size_t wstride_r, size_t n, int nrhs, const int* active, hipStream_t st);
+bool launch_mdot(cx<double>* h, int ldh, cx<double>* part, size_t part_cap, const cx<T>* Vb, size_t vstride_j,
+                 size_t vstride_r, int nvec, const cx<T>* w, size_t wstride_r, size_t n, int nrhs, const int* active,
+                 hipStream_t st);
 // w[r] += sign * sum_j h[r * ldh + j] * V_j[r], then w[r] *= post[r] if post;
 // w32 (same strides) receives an FP32 copy of the result if given
 template <typename Tw, typename Tv>
@@ -337,9 +341,9 @@ void launch_maxpy(cx<Tw>* w, size_t wstride_r, const cx<Tv>* Vb, size_t vstride_
 // Fused second Gram-Schmidt pass over FP64 vectors: w <- w - V h1, then
 // h2[r][j] = V_j^H w (j < nvec) and h2[r][nvec] = |w|^2, nvec <= GS_FUSED_MAXV
 constexpr int GS_FUSED_MAXV = 24;
-void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>* Vb, size_t vstride_j,
-                     size_t vstride_r, int nvec, cx<double>* w, size_t wstride_r, const cx<double>* h1, size_t n,
-                     int nrhs, const int* active, hipStream_t st);
+bool launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap, const cx<double>* Vb,
+                     size_t vstride_j, size_t vstride_r, int nvec, cx<double>* w, size_t wstride_r,
+                     const cx<double>* h1, size_t n, int nrhs, const int* active, hipStream_t st);
 // n2[r] = h2[r][nvec] - sum_{j<nvec} |h2[r][j]|^2, inv[r] = 1/sqrt(n2[r]) (0 if not positive)
 void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs,
                     const int* active, hipStream_t st);

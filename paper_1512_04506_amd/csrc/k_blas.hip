@@ -338,22 +338,17 @@ void launch_inv_norm(double* s, const cx<double>* n2, int nrhs, int* status, hip
   inv_norm_kernel<<<1, 64, 0, st>>>(s, n2, nrhs, status);
 }
 
-int blas_nchunks(size_t n) {
-  size_t c = (n + 8191) / 8192;
-  if (c < 1) c = 1;
-  if (c > 512) c = 512;
-  return (int)c;
-}
-
 template <typename T>
-void launch_mdot(cx<double>* h, int ldh, cx<double>* part, const cx<T>* Vb, size_t vsj, size_t vsr, int nvec,
-                 const cx<T>* w, size_t wsr, size_t n, int nrhs, const int* active, hipStream_t st) {
-  if (nrhs <= 0 || nvec <= 0 || nvec > MAX_MDOT_VECS) return;
+bool launch_mdot(cx<double>* h, int ldh, cx<double>* part, size_t part_cap, const cx<T>* Vb, size_t vsj, size_t vsr,
+                 int nvec, const cx<T>* w, size_t wsr, size_t n, int nrhs, const int* active, hipStream_t st) {
+  if (nrhs <= 0 || nvec <= 0) return true;
+  if (nvec > MAX_MDOT_VECS || mdot_part_entries(n, nvec, nrhs) > part_cap) return false;
   const int nchunk = blas_nchunks(n);
   const size_t chunk = (n + nchunk - 1) / nchunk;
   mdot_partial_kernel<T><<<dim3(nchunk, nrhs), BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, n, chunk, nchunk,
                                                             active);
   mdot_final_kernel<<<dim3(nvec, nrhs), 64, 0, st>>>(h, ldh, part, nvec, nchunk, active);
+  return true;
 }
 
 template <typename Tw, typename Tv>
@@ -365,10 +360,11 @@ void launch_maxpy(cx<Tw>* w, size_t wsr, const cx<Tv>* Vb, size_t vsj, size_t vs
       <<<dim3(grid_for(n), nrhs), BT, 0, st>>>(w, wsr, Vb, vsj, vsr, nvec, h, ldh, sign, n, active, post, w32);
 }
 
-void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>* Vb, size_t vsj, size_t vsr,
-                     int nvec, cx<double>* w, size_t wsr, const cx<double>* h1, size_t n, int nrhs, const int* active,
-                     hipStream_t st) {
-  if (nrhs <= 0 || nvec <= 0 || nvec > GS_FUSED_MAXV) return;
+bool launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap, const cx<double>* Vb, size_t vsj,
+                     size_t vsr, int nvec, cx<double>* w, size_t wsr, const cx<double>* h1, size_t n, int nrhs,
+                     const int* active, hipStream_t st) {
+  if (nrhs <= 0 || nvec <= 0) return true;
+  if (nvec > GS_FUSED_MAXV || mdot_part_entries(n, nvec + 1, nrhs) > part_cap) return false;
   const int nchunk = blas_nchunks(n);
   const size_t chunk = (n + nchunk - 1) / nchunk;
   // the narrowest instance that holds nvec basis entries per element (fewer
@@ -384,6 +380,7 @@ void launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, const cx<double>
     gs_fused_kernel<GS_FUSED_MAXV><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk,
                                                         active);
   mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
+  return true;
 }
 
 void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs, const int* active,
@@ -422,9 +419,9 @@ void launch_arnoldi_solve(ArnoldiState s, int nrhs, hipStream_t st) {
   arnoldi_solve_kernel<<<1, 64, 0, st>>>(s, nrhs);
 }
 
-template void launch_mdot<double>(cx<double>*, int, cx<double>*, const cx<double>*, size_t, size_t, int,
+template bool launch_mdot<double>(cx<double>*, int, cx<double>*, size_t, const cx<double>*, size_t, size_t, int,
                                   const cx<double>*, size_t, size_t, int, const int*, hipStream_t);
-template void launch_mdot<float>(cx<double>*, int, cx<double>*, const cx<float>*, size_t, size_t, int,
+template bool launch_mdot<float>(cx<double>*, int, cx<double>*, size_t, const cx<float>*, size_t, size_t, int,
                                  const cx<float>*, size_t, size_t, int, const int*, hipStream_t);
 #define INST2(A, B)                                                                                                   \
   template void launch_maxpy<A, B>(cx<A>*, size_t, const cx<B>*, size_t, size_t, int, const cx<double>*, int, double, \

@@ -127,3 +127,60 @@ def test_setup_composition_with_decoupled_blocks():
         # one power fewer is far off (the check has teeth)
         assert relerr(V[j].reshape(-1), D @ x / np.linalg.norm(D @ x)) > 1e-3
     assert relerr(M.W, coarse.orthonormalise(M.blk, V)) < 1e-12
+
+
+def _dense_vcycle_case(nu):
+    """A small lattice where the V-cycle's pieces are exact: block solves by
+    many MR steps (to rounding), coarse solve to 1e-14.  Returns the oracle
+    MG object and the dense D, B, R, P it is checked against."""
+    Ls, bs, ntv = (4, 4, 2, 2), (2, 2, 1, 1), 4
+    U = synth.su3_field(Ls, 0.5, 63)
+    p = mg.Params(Ls, bs, -0.2, 1.0, ntv, nu=nu, n_mr=80, coarse_tol=1e-14, coarse_restart=64,
+                  coarse_maxit=640)
+    M = mg.MG(p, U)
+    M.set_basis(coarse.orthonormalise(M.blk, synth.gaussian_spinors(Ls, ntv, 64)))
+    shp = (Ls[3], Ls[2], Ls[1], Ls[0], 4, 3)
+    D = dense_from_apply(M.D, shp)
+    B = dense_from_apply(lambda q: dirac.apply_B(U, M.A, q, Ls, bs), shp)
+    R = dense_from_apply(lambda q: coarse.restrict(M.blk, M.W, q), shp)
+    P = R.conj().T
+    return M, shp, D, B, R, P
+
+
+def _schwarz(blk, D, B, y, x0, nu):
+    """nu red/black multiplicative Schwarz cycles with exact block inverses
+    (dense algebra), started from x0."""
+    x = x0.copy()
+    masks = [blk.colour_mask_field(c).reshape(-1).astype(bool) for c in (0, 1)]
+    for _ in range(nu):
+        for m in masks:
+            r = y - D @ x
+            e = np.zeros_like(x)
+            e[m] = np.linalg.solve(B[np.ix_(m, m)], r[m])
+            x = x + e
+    return x
+
+
+@pytest.mark.parametrize("nu", [1, 3])
+def test_vcycle_composition_dense(nu):
+    """Pin of Alg. 1 (with Alg. 2 and Alg. 3): the coarse-grid correction
+    is x0 = P (R D P)^{-1} R y, and the smoother starts from it:
+    x = S^nu(y; x0).  Both checked against dense algebra with exact block
+    and coarse solves.  Two wrong compositions miss by far: the smoother
+    from zero without the correction, and the correction applied after the
+    smoother instead of before it."""
+    M, shp, D, B, R, P = _dense_vcycle_case(nu)
+    y = synth.gaussian_spinors(M.p.L, 1, 65)[0]
+    yv = y.reshape(-1)
+    Dc = R @ D @ P
+    x0 = P @ np.linalg.solve(Dc, R @ yv)
+    assert relerr(M.cgc(y).reshape(-1), x0) < 1e-11
+    want = _schwarz(M.blk, D, B, yv, x0, nu)
+    got = M.vcycle(y).reshape(-1)
+    assert relerr(got, want) < 1e-10
+    # teeth: no coarse-grid correction at all
+    no_cgc = _schwarz(M.blk, D, B, yv, np.zeros_like(yv), nu)
+    assert relerr(got, no_cgc) > 1e-3
+    # teeth: the correction after the smoother (post- instead of pre-smoothing order)
+    post = no_cgc + P @ np.linalg.solve(Dc, R @ (yv - D @ no_cgc))
+    assert relerr(got, post) > 1e-3

@@ -87,3 +87,73 @@ def random_su3_gauge_transform(L, seed):
     Lx, Ly, Lz, Lt = L
     U = su3_field((Lx, Ly, Lz, Lt), 1.0, seed)
     return U[..., 0, :, :].copy()
+
+
+# --------------------------------------------------------------------------
+# Counter-based draws for the seeded start of the setup.  The library draws
+# its random starting test vectors on the device when the caller passes
+# none; this is an independent host implementation of the same published
+# generator, so that both sides can start from identical vectors:
+#   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+#   easy as 1, 2, 3", SC 2011): 10 rounds of two 32x32 -> 64-bit products
+#   with multipliers 0xD2511F53 and 0xCD9E8D57, the key bumped by the Weyl
+#   constants 0x9E3779B9 and 0xBB67AE85 between rounds;
+#   two 53-bit uniforms per call, u = (a >> 5) 2^-27 + (b >> 6) 2^-53 in
+#   [0, 1) from the word pairs (x0, x1) and (x2, x3);
+#   one Box-Muller pair per call: re = rho cos(2 pi u2), im = rho sin(2 pi u2),
+#   rho = sqrt(-2 log(1 - u1)).
+# Complex element i of the canonical array [n][t][z][y][x][spin][colour]
+# uses the counter (i mod 2^32, i >> 32, 0, 0) and the key (seed mod 2^32,
+# seed >> 32).
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 on arrays: ctr (4, N) and key (2, N) of uint32-valued
+    integers; returns (4, N) uint64 arrays holding 32-bit words."""
+    m32 = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x, dtype=np.uint64) & m32 for x in ctr]
+    k = [np.asarray(x, dtype=np.uint64) & m32 for x in key]
+    for rnd in range(10):
+        if rnd:
+            k = [(k[0] + np.uint64(_PHILOX_W[0])) & m32, (k[1] + np.uint64(_PHILOX_W[1])) & m32]
+        p0 = np.uint64(_PHILOX_M[0]) * c[0]
+        p1 = np.uint64(_PHILOX_M[1]) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & m32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & m32
+        c = [hi1 ^ c[1] ^ k[0], lo1, hi0 ^ c[3] ^ k[1], lo0]
+    return c
+
+
+def philox_gaussian_spinors(L, n, seed):
+    """n complex Gaussian spinor fields drawn as the library draws them for a
+    setup started without test vectors (see above)."""
+    Lx, Ly, Lz, Lt = L
+    N = n * Lt * Lz * Ly * Lx * 12
+    out = np.empty(N, dtype=np.complex128)
+    seed = int(seed) & ((1 << 64) - 1)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    step = 1 << 20
+    for s in range(0, N, step):
+        i = np.arange(s, min(N, s + step), dtype=np.uint64)
+        z = np.zeros_like(i)
+        x = philox4x32_10((i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), z, z),
+                          (np.full_like(i, key[0]), np.full_like(i, key[1])))
+        u1 = (x[0] >> np.uint64(5)).astype(np.float64) * 2.0 ** -27 + (x[1] >> np.uint64(6)).astype(np.float64) * 2.0 ** -53
+        u2 = (x[2] >> np.uint64(5)).astype(np.float64) * 2.0 ** -27 + (x[3] >> np.uint64(6)).astype(np.float64) * 2.0 ** -53
+        rho = np.sqrt(-2.0 * np.log(1.0 - u1))
+        out[s:s + len(i)] = rho * np.cos(2.0 * np.pi * u2) + 1j * rho * np.sin(2.0 * np.pi * u2)
+    return out.reshape(n, Lt, Lz, Ly, Lx, 4, 3)
+
+
+def network_weights(channels, seed):
+    """Random starting weights of the test-vector network: one complex array
+    (C_out, C_in, 18) per layer for the channel counts channels = (C_0, C_1,
+    ..., C_L), entries complex Gaussian with variance 1 / (18 C_in)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        g = rng.standard_normal((cout, cin, 18, 2)) / np.sqrt(2.0 * 18 * cin)
+        out.append(g[..., 0] + 1j * g[..., 1])
+    return out

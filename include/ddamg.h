@@ -237,6 +237,25 @@ int dirac_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs, in
  * with coarse sites in the internal order (even coarse sites first). */
 int coarse_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs);
 
+/* ---- no-allocation variant -------------------------------------------
+ * For callers that cannot allocate device memory during a call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * dirac_apply_noalloc computes what dirac_apply computes, with the same
+ * kernels and the same result, but stages the internal-layout copies of in
+ * and out in a fixed device array of DDAMG_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends (its address
+ * is looked up once per device, at ddamg_create), instead of workspace that
+ * dirac_apply allocates on first use and whenever nrhs grows.  It calls no
+ * hipMalloc, hipFree or allocating library routine.
+ * Limit: 2 * nrhs * 12 * V * e bytes (each half rounded up to 256) must fit,
+ * e = 16 for DDAMG_FP64 and 8 otherwise; larger calls return DDAMG_EARG
+ * before any work.  Every call on one GPU, from any context or stream, uses
+ * that GPU's one array: calls that overlap in time on one GPU race, so
+ * serialise them (e.g. one stream).  Nothing in the array is read before
+ * this call writes it.  Asynchronous; out != in; 1 <= nrhs <= max_rhs. */
+#define DDAMG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int dirac_apply_noalloc(ddamg_ctx* ctx, double* out, const double* in, int nrhs, int prec);
+
 /* Per-kernel-class timing for profiling: when enabled, every launch of the
  * classes below is bracketed by HIP events recorded on the context's stream
  * and the elapsed times are summed (the brackets add a few microseconds of

@@ -26,7 +26,7 @@ EXPORTS = (
     "ddamg_export_clover", "mg_apply", "dirac_apply", "coarse_apply", "mg_restrict", "mg_prolong", "solve",
     "ddamg_get_stats", "ddamg_reset_stats", "dirac_apply_internal", "coarse_apply_internal", "ddamg_volume",
     "ddamg_nblocks", "ddamg_set_kernel_timing", "ddamg_get_kernel_times", "ddamg_import_tv",
-    "ddamg_import_coarse", "ddamg_set_allocator",
+    "ddamg_import_coarse", "ddamg_set_allocator", "dirac_apply_noalloc",
 )
 KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
                 "setup_galerkin", "residual")
@@ -90,6 +90,7 @@ def _load():
         "ddamg_export_clover": (i32, [vp, dp]),
         "mg_apply": (i32, [vp, dp, dp, i32]),
         "dirac_apply": (i32, [vp, dp, dp, i32, i32]),
+        "dirac_apply_noalloc": (i32, [vp, dp, dp, i32, i32]),
         "coarse_apply": (i32, [vp, dp, dp, i32]),
         "mg_restrict": (i32, [vp, dp, dp, i32]),
         "mg_prolong": (i32, [vp, dp, dp, i32]),
@@ -251,6 +252,10 @@ class Context:
     def dirac_apply(self, out, inp, nrhs, prec=FP64):
         b = self.fine_bytes(nrhs)
         return self._check(lib.dirac_apply(self.h, _ptr(out, "out", b), _ptr(inp, "in", b), nrhs, prec))
+
+    def dirac_apply_noalloc(self, out, inp, nrhs, prec=FP64):
+        b = self.fine_bytes(nrhs)
+        return self._check(lib.dirac_apply_noalloc(self.h, _ptr(out, "out", b), _ptr(inp, "in", b), nrhs, prec))
 
     def dirac_apply_internal(self, out, inp, nrhs, prec):
         es = 16 if prec == FP64 else 8

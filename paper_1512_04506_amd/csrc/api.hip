@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -111,6 +112,30 @@ struct DevBuf {
 
 std::string g_create_error;
 
+// Staging area of dirac_apply_noalloc: one copy of this array on every GPU
+// the library runs on, held until the process ends.  Its host-side name is
+// not a device address: resolve_scratch() looks up the address on the
+// current device once, at context creation, and contexts keep it.
+__device__ __align__(256) unsigned char scratch[DDAMG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* resolve_scratch() {
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Fail{DDAMG_EHIP, "device ordinal out of range"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Fail{DDAMG_EHIP, "hipGetSymbolAddress returned NULL for the staging array"};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // Opt-in per-kernel-class timing with HIP events recorded on the context's
 // stream around each launch; elapsed times are collected at the next
 // synchronisation point (or when many records are pending).
@@ -199,6 +224,7 @@ struct ddamg_ctx {
   // canonical <-> internal staging
   DevBuf stage_in, stage_out;
   size_t stage_rhs = 0;
+  void* scratch = nullptr;  // this device's address of the no-allocation staging array
   std::unique_ptr<SolverBase> sol;
   KTimer kt;
   bool setup_done = false;
@@ -1016,6 +1042,8 @@ int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg
   try {
     c->p = *p;
     c->st = static_cast<hipStream_t>(stream);
+    c->scratch = resolve_scratch();
+    preload_dslash_code();
     Geom& g = c->g;
     g.V = 1;
     g.vblock = 1;
@@ -1270,8 +1298,28 @@ int dirac_apply_internal(ddamg_ctx* c, void* out, const void* in, int nrhs, int 
   GUARD_END
 }
 
-int dirac_apply(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec) {
-  if (!c) return DDAMG_EARG;
+// out = D in on canonical fields through internal-layout copies a (of in)
+// and b (of out), each nrhs * 12 * V elements of the precision's type
+static int dirac_apply_staged(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec, void* a, void* b) {
+  const Geom& g = c->g;
+  const cx<double>* cin = reinterpret_cast<const cx<double>*>(in);
+  cx<double>* cout = reinterpret_cast<cx<double>*>(out);
+  if (prec == DDAMG_FP64) {
+    launch_spinor_to_internal<double>(static_cast<cx<double>*>(a), cin, g, nrhs, c->st);
+    int rc = dirac_apply_internal(c, b, a, nrhs, prec);
+    if (rc) return rc;
+    launch_spinor_to_canonical<double>(cout, static_cast<cx<double>*>(b), g, nrhs, c->st);
+  } else {
+    launch_spinor_to_internal<float>(static_cast<cx<float>*>(a), cin, g, nrhs, c->st);
+    int rc = dirac_apply_internal(c, b, a, nrhs, prec);
+    if (rc) return rc;
+    launch_spinor_to_canonical<float>(cout, static_cast<cx<float>*>(b), g, nrhs, c->st);
+  }
+  check_launch("dirac_apply");
+  return DDAMG_OK;
+}
+
+static int dirac_apply_args(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec) {
   if (!out || !in || out == in) {
     c->err = "out and in must be distinct non-NULL pointers";
     return DDAMG_EARG;
@@ -1281,28 +1329,35 @@ int dirac_apply(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec)
     c->err = "unknown precision";
     return DDAMG_EARG;
   }
-  GUARD_BEGIN
-  const Geom& g = c->g;
-  c->ensure_stage(nrhs);
-  const cx<double>* cin = reinterpret_cast<const cx<double>*>(in);
-  cx<double>* cout = reinterpret_cast<cx<double>*>(out);
-  if (prec == DDAMG_FP64) {
-    cx<double>* a = c->stage_in.get<cx<double>>();
-    cx<double>* b = c->stage_out.get<cx<double>>();
-    launch_spinor_to_internal<double>(a, cin, g, nrhs, c->st);
-    int rc = dirac_apply_internal(c, b, a, nrhs, prec);
-    if (rc) return rc;
-    launch_spinor_to_canonical<double>(cout, b, g, nrhs, c->st);
-  } else {
-    cx<float>* a = c->stage_in.get<cx<float>>();
-    cx<float>* b = c->stage_out.get<cx<float>>();
-    launch_spinor_to_internal<float>(a, cin, g, nrhs, c->st);
-    int rc = dirac_apply_internal(c, b, a, nrhs, prec);
-    if (rc) return rc;
-    launch_spinor_to_canonical<float>(cout, b, g, nrhs, c->st);
-  }
-  check_launch("dirac_apply");
   return DDAMG_OK;
+}
+
+int dirac_apply(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec) {
+  if (!c) return DDAMG_EARG;
+  if (int e = dirac_apply_args(c, out, in, nrhs, prec)) return e;
+  GUARD_BEGIN
+  c->ensure_stage(nrhs);
+  return dirac_apply_staged(c, out, in, nrhs, prec, c->stage_in.p, c->stage_out.p);
+  GUARD_END
+}
+
+int dirac_apply_noalloc(ddamg_ctx* c, double* out, const double* in, int nrhs, int prec) {
+  if (!c) return DDAMG_EARG;
+  if (int e = dirac_apply_args(c, out, in, nrhs, prec)) return e;
+  const size_t es = prec == DDAMG_FP64 ? sizeof(cx<double>) : sizeof(cx<float>);
+  const size_t half = ((size_t)nrhs * 12 * c->g.V * es + 255) / 256 * 256;
+  if (2 * half > DDAMG_NOALLOC_SCRATCH_BYTES) {
+    c->err = "dirac_apply_noalloc: 2 * nrhs * 12 * V * " + std::to_string(es) + " bytes of staging exceed "
+             "DDAMG_NOALLOC_SCRATCH_BYTES (" + std::to_string((size_t)DDAMG_NOALLOC_SCRATCH_BYTES) + ")";
+    return DDAMG_EARG;
+  }
+  if (!c->scratch) {
+    c->err = "dirac_apply_noalloc: no staging array on this device";
+    return DDAMG_ESTATE;
+  }
+  GUARD_BEGIN
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  return dirac_apply_staged(c, out, in, nrhs, prec, base, base + half);
   GUARD_END
 }
 

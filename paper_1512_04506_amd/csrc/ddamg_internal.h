@@ -262,6 +262,9 @@ template <typename Tin, typename Tout, typename S, typename Tc>
 void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, int mode,
                    int mu, int chi_in, size_t in_rstride, size_t out_rstride, hipStream_t st);
 
+// loads the code object of the dslash kernels (see k_dslash.hip)
+void preload_dslash_code();
+
 // SAP: one colour phase of multiplicative Schwarz with n_mr MR steps per
 // block, in place on x, for nrhs fields.
 template <typename T, typename S>

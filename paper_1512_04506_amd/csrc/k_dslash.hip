@@ -390,6 +390,15 @@ void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, con
   }
 }
 
+// The runtime loads a file's code object (device memory for its kernels)
+// when one of them is first used; asking for a kernel's attributes does it
+// now, so that later applies, including the one that must not allocate,
+// find the code resident.
+void preload_dslash_code() {
+  hipFuncAttributes a;
+  (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dslash_staged_kernel<double, double, double, double, 1>));
+}
+
 #define INST(Tin, Tout, S, Tc)                                                                                   \
   template void launch_dslash<Tin, Tout, S, Tc>(cx<Tout>*, const cx<Tin>*, const GaugeView<S>&, const Geom&, int, \
                                                 int, int, int, size_t, size_t, hipStream_t);

@@ -144,6 +144,142 @@ def kernel_rooflines(dd, torch, ctx, w, reps=50):
     return out
 
 
+def coarse_iteration_cost(dd, torch, w, U_d, tv_d, f_d, its=(5, 30), reps=5):
+    """Wall-clock cost of one coarse GMRES iteration (Alg. 2) inside the
+    V-cycle at the workload, in deterministic mode (a fixed number of coarse
+    iterations, no tolerance test): (T(its[1]) - T(its[0])) / (its[1] -
+    its[0]) for V-cycles of all rhs, with the host reading the convergence
+    flags after every iteration ("sync_each", the device idles meanwhile)
+    and with the pipelined test ("pipelined": nothing read with a fixed
+    count).  Also the device time of the coarse kernels per iteration."""
+    nrhs = w["nrhs"]
+    out = {"coarse_fixed_its": list(its), "nrhs": nrhs}
+    times = {}
+    for n_its in its:
+        p = dd.default_params(L=w["L"], block=w["block"], m0=w["m0"], csw=1.0, ntv=w["ntv"], prec=dd.MIXED16,
+                              max_rhs=nrhs, coarse_fixed_its=n_its, coarse_restart=max(its))
+        ctx = dd.Context(p, U_d)
+        ctx.mg_setup(tv_d)
+        x = torch.zeros_like(f_d)
+        for mode in ("sync_each", "pipelined"):
+            ctx.set_coarse_host_sync(mode == "sync_each")
+            ctx.mg_apply(x, f_d, nrhs)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                ctx.mg_apply(x, f_d, nrhs)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            times[(mode, n_its)] = sorted(ts)[len(ts) // 2]
+        ctx.set_coarse_host_sync(False)
+        ctx.set_kernel_timing(True)
+        ctx.mg_apply(x, f_d, nrhs)
+        kt = ctx.kernel_times()
+        ctx.set_kernel_timing(False)
+        if n_its == its[1]:
+            out["device_ms_per_iteration_at_%d" % n_its] = (kt["coarse"][0] + kt["coarse_gs"][0]) / n_its
+        ctx.close()
+        del x
+        torch.cuda.empty_cache()
+    d = its[1] - its[0]
+    for mode in ("sync_each", "pipelined"):
+        out["ms_per_iteration_" + mode] = (times[(mode, its[1])] - times[(mode, its[0])]) / d
+        out["vcycle_ms_%s_%d_its" % (mode, its[1])] = times[(mode, its[1])]
+    return out
+
+
+def _field_worker(a):
+    import synth
+    L, eps, seed = a
+    return synth.su3_field(L, eps, seed)
+
+
+def generated_fields(L, eps, seeds, workers):
+    """Seeded gauge fields drawn on the host in a process pool (children
+    started fresh: they import only numpy and the input generators)."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_field_worker, [(L, eps, s) for s in seeds])
+
+
+def learned_eval(dd, torch, w, args):
+    """The learned test-vector proposal: train the network on the aggregate
+    bases of plain setups on generated 16^4 fields (eps 0.5, m0 -0.2, 4^4
+    blocks, N_tv of the workload), then on the workload compare setups:
+    plain (Alg. 4: three smoother passes, n_setup V-cycle passes), learned
+    (the network's proposal, no smoother passes, fewer V-cycle passes) and
+    the same short setup from random vectors (what the network adds)."""
+    import numpy as np
+    from paper_1512_04506_amd import learned_setup as ls
+    ntv = w["ntv"]
+    Lt = (16, 16, 16, 16)
+    t0 = time.perf_counter()
+    nf = args.train_fields
+    fields = generated_fields(Lt, 0.5, [700 + k for k in range(nf)], min(16, nf))
+    log("learned: %d training fields generated in %.1f s" % (nf, time.perf_counter() - t0))
+    net = dd.Net(ls.channels_for(ntv))
+    import synth
+    net.set_weights(torch.from_numpy(np.concatenate([x.reshape(-1) for x in synth.network_weights(
+        ls.channels_for(ntv), 7)]).astype(np.complex64)).cuda())
+    pt = dd.default_params(L=Lt, block=(4, 4, 4, 4), m0=-0.2, csw=1.0, ntv=ntv, prec=dd.MIXED16, max_rhs=ntv)
+    samples = []
+    for k in range(nf):
+        Ud = torch.from_numpy(fields[k]).cuda()
+        s, _ = ls.training_samples(net, [Ud], pt, seed0=1000 + k)
+        samples += s
+        del Ud
+    del fields
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ls.train(net, samples, args.train_epochs, args.train_lr, decay=0.5,
+                    decay_every=max(1, args.train_epochs // 3), log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    res = {"train_fields": nf, "epochs": args.train_epochs, "lr": args.train_lr, "train_s": train_s,
+           "steps": nf * args.train_epochs, "ms_per_step": train_s * 1e3 / (nf * args.train_epochs),
+           "loss_per_epoch": hist, "channels": list(ls.channels_for(ntv)), "weights": int(net.nw)}
+    # the workload: plain against learned and random short setups
+    U, tv, f = make_inputs(w)
+    U_d = torch.from_numpy(U).cuda()
+    f_d = torch.from_numpy(f).cuda()
+    del U, tv
+    nrhs = w["nrhs"]
+    rows = []
+    for name, init_passes, n_setup, start in [("plain", 3, 3, "random"), ("learned", 0, 1, "net"),
+                                              ("random_short", 0, 1, "random"), ("learned", 0, 2, "net"),
+                                              ("random_short", 0, 2, "random")]:
+        p = dd.default_params(L=w["L"], block=w["block"], m0=w["m0"], csw=1.0, ntv=ntv, prec=dd.MIXED16,
+                              max_rhs=max(nrhs, ntv), init_passes=init_passes, n_setup=n_setup, seed=302)
+        ctx = dd.Context(p, U_d)
+        setups = []
+        for rep_ in range(3):
+            if start == "net":
+                prop_ms, set_ms = ls.propose_setup(net, ctx, seed=5000 + rep_)
+            else:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.mg_setup()
+                torch.cuda.synchronize()
+                prop_ms, set_ms = 0.0, (time.perf_counter() - t0) * 1e3
+            setups.append((prop_ms, set_ms))
+        u = torch.zeros_like(f_d)
+        rc, st = ctx.solve(u, f_d, nrhs, 1e-10)
+        r = {"setup": name, "init_passes": init_passes, "n_setup": n_setup,
+             "proposal_ms": min(x[0] for x in setups), "setup_ms": min(x[1] for x in setups),
+             "outer_iterations": st["outer_iterations"], "solve_ms": st["solve_ms"], "converged": rc == 0}
+        r["setup_total_ms"] = r["proposal_ms"] + r["setup_ms"]
+        rows.append(r)
+        log("learned eval:", json.dumps(r))
+        ctx.close()
+        del u
+        torch.cuda.empty_cache()
+    res["workload"] = w["name"]
+    res["setups"] = rows
+    net.close()
+    return res
+
+
 def sap_flops_per_site(block, n_mr):
     """Algorithmic flops of one SAP colour phase per site of that colour and
     rhs: residual y - D x (1320 hop + 504 clover + 24), n_mr MR steps each
@@ -223,46 +359,99 @@ def measured_traffic(kind, workload):
     return None
 
 
-def cpu_baseline(w):
-    """Time the oracle (numpy, one thread) on a bounded sample and scale it to
-    the workload: the full setup + one-rhs solve on the 8^4 lattice with the
-    same parameters (smallest lattice with an even number of 4^4 blocks per
-    direction), scaled by the volume ratio (setup) and by volume ratio x nrhs
-    (solve; the oracle solves right-hand sides one after another)."""
-    code = r"""
+def _host_cpu():
+    """(cores this process may use, CPU model name)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+_ORACLE_CHILD = r"""
 import json, sys, time
 sys.path.insert(0, %r)
 import numpy as np
+import multiprocessing as mp
 import synth
-from oracle import mg
-L = (8, 8, 8, 8)
-U = synth.su3_field(L, %r, 301)
-p = mg.Params(L, %r, %r, 1.0, %d)
-M = mg.MG(p, U)
-t0 = time.perf_counter()
-M.setup(synth.gaussian_spinors(L, %d, 302))
-t1 = time.perf_counter()
-f = synth.point_sources(L)[0]
-u, st = M.solve(f)
-t2 = time.perf_counter()
-print(json.dumps(dict(setup=t1 - t0, solve=t2 - t1, its=st["iterations"], relres=st["relres"])))
-""" % (ROOT, w["eps"], tuple(w["block"]), w["m0"], w["ntv"], w["ntv"])
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+from oracle import mg, dirac
+
+def solve_one(args):
+    M, f = args
     t = time.perf_counter()
-    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    u, st = M.solve(f)
+    return time.perf_counter() - t, st["iterations"], mg.true_relres(M.D, u, f)
+
+def run(L, block, eps, m0, ntv, seeds, rhs, nrhs, workers):
+    U = synth.su3_field(L, eps, seeds[0])
+    p = mg.Params(L, block, m0, 1.0, ntv)
+    M = mg.MG(p, U)
+    t0 = time.perf_counter()
+    M.setup(synth.gaussian_spinors(L, ntv, seeds[1]))
+    t1 = time.perf_counter()
+    f = synth.point_sources(L)[:nrhs] if rhs == "point" else synth.gaussian_spinors(L, nrhs, 103)
+    with mp.get_context("fork").Pool(min(workers, nrhs)) as pool:
+        out = pool.map(solve_one, [(M, f[r]) for r in range(nrhs)])
+    t2 = time.perf_counter()
+    return dict(setup_s=t1 - t0, solve_s=t2 - t1, solve_cpu_s=sum(o[0] for o in out),
+                outer_its=[o[1] for o in out], relres_max=max(o[2] for o in out))
+
+if __name__ == "__main__":
+    cfg = json.loads(sys.argv[1])
+    print(json.dumps(run(**cfg)))
+"""
+
+
+def _oracle_run(cfg, cores, timeout):
+    """One oracle run in a fresh interpreter (no GPU in it): the setup in
+    one process (the oracle's setup is serial; numpy on more BLAS threads
+    made it slower: 201 s against 81 s on 8 threads for the 8^4 sample),
+    the right-hand sides solved in a process pool of min(cores, nrhs)
+    workers, every process on one BLAS thread."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = _ORACLE_CHILD % ROOT
+    p = subprocess.run([sys.executable, "-c", code, json.dumps(cfg)], capture_output=True, text=True, env=env,
+                       timeout=timeout)
     if p.returncode != 0:
-        raise RuntimeError(p.stderr)
-    r = json.loads(p.stdout.strip().splitlines()[-1])
+        raise RuntimeError(p.stderr[-500:])
+    return json.loads(p.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(w):
+    """The oracle (numpy, FP64) timed on this host's cores: the 4^4
+    workload measured in full (setup + solve), and the same parameters as
+    the workload on the 8^4 lattice (the smallest with an even number of
+    4^4 blocks per direction: setup + all rhs), which is scaled by the
+    volume ratio to the workload (an extrapolation, stated as such)."""
+    cores, model = _host_cpu()
+    t = time.perf_counter()
+    c1 = WORKLOADS["c1"]
+    m1 = _oracle_run(dict(L=c1["L"], block=c1["block"], eps=c1["eps"], m0=c1["m0"], ntv=c1["ntv"],
+                          seeds=c1["seeds"], rhs=c1["rhs"], nrhs=c1["nrhs"], workers=cores), cores, 600)
+    ms = _oracle_run(dict(L=(8, 8, 8, 8), block=w["block"], eps=w["eps"], m0=w["m0"], ntv=w["ntv"],
+                          seeds=w["seeds"], rhs=w["rhs"], nrhs=w["nrhs"], workers=cores), cores, 900)
     V = 1
     for x in w["L"]:
         V *= x
     scale = V / 8 ** 4
-    est = r["setup"] * scale + r["solve"] * scale * w["nrhs"]
-    return dict(value=est, unit="s", cores=1, kind="oracle",
-                sample="oracle setup + 1-rhs solve on 8^4 (same eps/m0/csw/blocks/Ntv, %.1f s wall, %d outer its, "
-                       "relres %.1e), scaled x%d volume for setup and x%d volume x %d rhs for the solve"
-                       % (time.perf_counter() - t, r["its"], r["relres"], scale, scale, w["nrhs"]),
-                sample_setup_s=r["setup"], sample_solve_s=r["solve"])
+    est = (ms["setup_s"] + ms["solve_s"]) * scale
+    return dict(value=est, unit="s", cores=min(cores, w["nrhs"]), host_cores=cores, cpu_model=model, kind="oracle",
+                cores_note="setup on 1 core (the oracle's setup is serial), rhs on a pool of min(cores, nrhs)",
+                sample="8^4 lattice with the workload's eps/m0/csw/blocks/Ntv: setup %.1f s (1 core) + %d rhs %.1f s "
+                       "(%d processes) measured, scaled x%d by volume to the workload (extrapolated); 4^4 workload "
+                       "measured in full: setup %.2f s + solve %.2f s; %.0f s wall in all"
+                       % (ms["setup_s"], w["nrhs"], ms["solve_s"], min(cores, w["nrhs"]), scale, m1["setup_s"],
+                          m1["solve_s"], time.perf_counter() - t),
+                measured={"c1_4x4x4x4": m1, "sample_8x8x8x8": ms}, extrapolated_to=w["name"])
 
 
 def main():
@@ -273,6 +462,12 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-coarse-cost", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="train the test-vector network and compare learned and plain setups (prints its own line)")
+    ap.add_argument("--train-fields", type=int, default=32)
+    ap.add_argument("--train-epochs", type=int, default=12)
+    ap.add_argument("--train-lr", type=float, default=2e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (a multi-GPU run would split "
@@ -283,6 +478,9 @@ def main():
     import paper_1512_04506_amd as dd
     w = WORKLOADS[args.workload]
     log("workload", w["name"])
+    if args.learned:
+        print(json.dumps({"learned_setup": learned_eval(dd, torch, w, args)}), flush=True)
+        return
     t = time.perf_counter()
     U, tv, f = make_inputs(w)
     log("inputs generated in %.1f s" % (time.perf_counter() - t))
@@ -293,10 +491,32 @@ def main():
     mixed = run_path(dd, torch, w, dd.MIXED16, U_d, tv_d, f_d, args.steps, args.warmup)
     roof = kernel_rooflines(dd, torch, mixed["ctx"], w)
     log("kernels:", json.dumps(roof))
+    # the solve with the host reading the coarse convergence flags after
+    # every coarse iteration, against the pipelined test (tolerance mode)
+    solve_sync = {}
+    for mode in ("sync_each", "pipelined"):
+        mixed["ctx"].set_coarse_host_sync(mode == "sync_each")
+        ts = []
+        for _ in range(2):
+            mixed["u"].zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mixed["ctx"].solve(mixed["u"], f_d, w["nrhs"], 1e-10)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        solve_sync[mode] = min(ts)
+    mixed["ctx"].set_coarse_host_sync(False)
+    log("solve ms by coarse convergence test:", json.dumps(solve_sync))
     st = mixed["stats"]
     mixed["ctx"].close()
     del mixed["ctx"], mixed["u"]
     torch.cuda.empty_cache()
+    coarse_cost = None
+    if not args.no_coarse_cost:
+        coarse_cost = coarse_iteration_cost(dd, torch, w, U_d, tv_d, f_d)
+        coarse_cost["solve_ms_sync_each"] = solve_sync["sync_each"]
+        coarse_cost["solve_ms_pipelined"] = solve_sync["pipelined"]
+        log("coarse iteration cost:", json.dumps(coarse_cost))
     fp64 = None
     if not args.no_fp64:
         fp64 = run_path(dd, torch, w, dd.FP64, U_d, tv_d, f_d, max(1, args.steps // 2), args.warmup)
@@ -326,6 +546,7 @@ def main():
         "kernel_times_ms": {k: round(v[0] / args.steps, 3) for k, v in mixed["kernel_times"].items()},
         "kernels_isolated": roof,
         "roofline": dominant_roofline(w, mixed["kernel_times"], dd.MIXED16),
+        "coarse_iteration_cost": coarse_cost,
     }
     line["roofline"]["traffic"] = measured_traffic(line["roofline"]["kernel"], w["name"])
     if fp64:

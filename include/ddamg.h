@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define DDAMG_ABI_VERSION 1
+#define DDAMG_ABI_VERSION 2
 
 /* precision of the preconditioner (smoother, R/P, coarse solve) */
 #define DDAMG_FP64 0     /* everything FP64 */
@@ -95,6 +95,12 @@ typedef struct {
   int32_t outer_maxit;     /* outer iteration cap */
   int32_t prec;            /* DDAMG_FP64, DDAMG_FP32 or DDAMG_MIXED16 */
   int32_t max_rhs;         /* largest nrhs of any later call (>= 1, <= 64) */
+  int32_t init_passes;     /* mg_setup's initial smoother passes on the start
+                              vectors, N_smoother = 1, 2, ..., init_passes from a
+                              zero guess (Alg. 4: 3); 0 uses the start vectors
+                              as they are (e.g. a ddamg_net_propose output) */
+  uint64_t seed;           /* key of the random starting test vectors that
+                              mg_setup draws when it is given none */
 } ddamg_params;
 
 typedef struct {
@@ -113,7 +119,8 @@ typedef struct {
 /* Fills *p with the defaults: block 4^4, m0 = 0, csw = 1, ntv = 24,
  * n_setup = 3, nu = 3, n_mr = 4, coarse_tol = 0.05, coarse_restart = 30,
  * coarse_maxit = 300, coarse_fixed_its = 0, outer_restart = 20,
- * outer_maxit = 2000, prec = DDAMG_MIXED16, max_rhs = 12. */
+ * outer_maxit = 2000, prec = DDAMG_MIXED16, max_rhs = 12, init_passes = 3,
+ * seed = 0. */
 void ddamg_default_params(ddamg_params* p);
 
 /* Checks p without touching the GPU.  Returns 0 or DDAMG_EARG and, if msg is
@@ -149,7 +156,13 @@ const char* ddamg_last_error(const ddamg_ctx* ctx);
  * smoothed with N_smoother = 1, 2, 3 from a zero guess, R and D_c are
  * built (aggregate Gram-Schmidt in FP64, D_c = R D P with backward couplings
  * from Eq. dagger), the vectors are normalised, then n_setup passes apply
- * the V-cycle to every test vector and rebuild R and D_c.  Synchronous. */
+ * the V-cycle to every test vector and rebuild R and D_c.  Synchronous.
+ * tv_init == NULL: the starting vectors are drawn on the device from the
+ * context's seed, complex element i of the canonical array (re, im ~ N(0,1))
+ * by Philox4x32-10 (Salmon et al., SC 2011) with counter (i mod 2^32,
+ * i >> 32, 0, 0) and key (seed mod 2^32, seed >> 32), whose output words
+ * (x0, x1, x2, x3) give u1 = (x0 >> 5) 2^-27 + (x1 >> 6) 2^-53, u2 likewise
+ * from (x2, x3), and Box-Muller sqrt(-2 log(1 - u1)) (cos, sin)(2 pi u2). */
 int mg_setup(ddamg_ctx* ctx, const double* tv_init);
 
 /* Replaces the aggregate basis by W (device, canonical [ntv][V][4][3],
@@ -256,6 +269,19 @@ int coarse_apply_internal(ddamg_ctx* ctx, void* out, const void* in, int nrhs);
 #define DDAMG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 int dirac_apply_noalloc(ddamg_ctx* ctx, double* out, const double* in, int nrhs, int prec);
 
+/* Convergence test of the coarse GMRES (Alg. 2), for timing comparisons.
+ * Default (each_iteration = 0): pipelined -- the per-rhs convergence flags
+ * of coarse iteration k are copied to pinned host memory behind its
+ * kernels, and the host reads them only after it has enqueued iteration
+ * k + 1, so the device never waits for the host's decision; every kernel of
+ * an iteration is predicated on the flags, so the one iteration enqueued
+ * past convergence does no work and changes no result.  With a fixed
+ * iteration count (coarse_fixed_its > 0) nothing is read at all.
+ * each_iteration = 1: the host waits for the flags after every iteration
+ * (the device drains and idles while the next launches are issued).
+ * Results are identical either way. */
+int ddamg_set_coarse_host_sync(ddamg_ctx* ctx, int each_iteration);
+
 /* Per-kernel-class timing for profiling: when enabled, every launch of the
  * classes below is bracketed by HIP events recorded on the context's stream
  * and the elapsed times are summed (the brackets add a few microseconds of
@@ -276,6 +302,63 @@ int dirac_apply_noalloc(ddamg_ctx* ctx, double* out, const double* in, int nrhs,
 #define DDAMG_NKERNEL_KINDS 10
 int ddamg_set_kernel_timing(ddamg_ctx* ctx, int on);
 int ddamg_get_kernel_times(ddamg_ctx* ctx, double* ms, int64_t* count, int64_t* rhs, int n);
+
+/* ---- learned proposal of test vectors --------------------------------
+ * Not in the paper: the setup of Alg. 4 starts from random vectors; a
+ * ddamg_net is a small gauge-covariant network that maps random fields to
+ * proposed test vectors instead, trained on the device against the
+ * aggregate basis (Alg. 5) of finished plain setups.
+ *
+ * Network: layers l = 0 .. L-1 map C_l channel fields phi_j (spinor fields)
+ * to C_{l+1}:  psi_i(x) = sum_j [(a + b g5) phi_j(x) + sum_mu sum_s (c + d
+ * g_mu) T_mu,s phi_j(x)] with the parallel transports T_mu,+ phi(x) =
+ * U_mu(x) phi(x + mu), T_mu,- phi(x) = U_mu(x - mu)^dag phi(x - mu) under
+ * the boundary conditions of D; between layers every channel passes the
+ * gate phi / sqrt(1 + |phi(x)|^2 / 12) (|.| over spin and colour).  Weights,
+ * complex64 (interleaved float pairs), layer after layer, each
+ * [C_{l+1}][C_l][18]: index 0 = a, 1 = b, 2 + 2h = c and 3 + 2h = d of hop
+ * h = 2 mu + s (s = 0 forward, 1 backward).  C_0 input fields (random),
+ * C_L = ntv outputs.
+ *
+ * Span loss against an aggregate basis T (orthonormal per aggregate):
+ * (1 / (N_A ntv)) sum_A ||(1 - P_A) T_A||_F^2, P_A the orthogonal
+ * projector onto the span of the proposal on aggregate A; 0 when every
+ * aggregate's proposal spans its target.  Gradients are dL/dRe w + i dL/dIm w.
+ *
+ * Random input fields: canonical complex128 [C_0][V][4][3] (device), or NULL
+ * to draw them from seed exactly as mg_setup draws start vectors.
+ * Arithmetic FP32.  A ddamg_net is not thread-safe; its calls synchronise
+ * its stream. */
+typedef struct ddamg_net ddamg_net;
+
+/* channels[0 .. nlayers]: C_0 .. C_L, each in [1, 32], 1 <= nlayers <= 8;
+ * weights start at zero; stream: hipStream_t (NULL = default). */
+int ddamg_net_create(const int32_t* channels, int32_t nlayers, void* stream, ddamg_net** out);
+int ddamg_net_destroy(ddamg_net* net);
+const char* ddamg_net_last_error(const ddamg_net* net);
+/* number of complex weights (float pairs) */
+int64_t ddamg_net_num_weights(const ddamg_net* net);
+/* device complex64 weights in the layout above; set resets Adam's state */
+int ddamg_net_set_weights(ddamg_net* net, const float* w);
+int ddamg_net_get_weights(ddamg_net* net, float* w);
+/* Adds a training sample: the links of ctx (FP32) and its current aggregate
+ * basis (dequantised to FP32) as the target.  ctx must have finished a
+ * setup, have ntv = C_L, and all samples one lattice and blocking.
+ * *index (may be NULL) receives the sample number. */
+int ddamg_net_add_sample(ddamg_net* net, ddamg_ctx* ctx, int32_t* index);
+/* Span loss of the proposal for sample's links and input fields against
+ * its target; grad (device, complex64, weight layout, may be NULL)
+ * receives the gradient.  DDAMG_ENUMERIC if the proposal has rank below
+ * ntv on an aggregate. */
+int ddamg_net_loss_grad(ddamg_net* net, int32_t sample, const double* noise, uint64_t seed, double* loss, float* grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, on real and imaginary
+ * parts) with learning rate lr on the gradient of sample with input fields
+ * drawn from seed; *loss (may be NULL) receives the loss before the step. */
+int ddamg_net_train_step(ddamg_net* net, int32_t sample, uint64_t seed, float lr, double* loss);
+/* Proposed test vectors on the lattice and links of ctx (ntv = C_L):
+ * out canonical complex128 [ntv][V][4][3], for mg_setup (with init_passes
+ * = 0 it starts the setup from them as they are). */
+int ddamg_net_propose(ddamg_net* net, ddamg_ctx* ctx, const double* noise, uint64_t seed, double* out);
 
 /* Geometry queries: number of sites and of blocks. */
 int64_t ddamg_volume(const ddamg_ctx* ctx);

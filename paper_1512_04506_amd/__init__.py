@@ -16,6 +16,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddamg.so")
 
+ABI_VERSION = 2  # DDAMG_ABI_VERSION of include/ddamg.h this binding follows
 FP64, FP32, MIXED16 = 0, 1, 2
 OK, NOT_CONVERGED = 0, 1
 ERRORS = {-1: "invalid argument", -2: "wrong state", -3: "HIP error", -4: "out of memory", -5: "numerical failure"}
@@ -26,7 +27,10 @@ EXPORTS = (
     "ddamg_export_clover", "mg_apply", "dirac_apply", "coarse_apply", "mg_restrict", "mg_prolong", "solve",
     "ddamg_get_stats", "ddamg_reset_stats", "dirac_apply_internal", "coarse_apply_internal", "ddamg_volume",
     "ddamg_nblocks", "ddamg_set_kernel_timing", "ddamg_get_kernel_times", "ddamg_import_tv",
-    "ddamg_import_coarse", "ddamg_set_allocator", "dirac_apply_noalloc",
+    "ddamg_import_coarse", "ddamg_set_allocator", "dirac_apply_noalloc", "ddamg_set_coarse_host_sync",
+    "ddamg_net_create", "ddamg_net_destroy", "ddamg_net_last_error", "ddamg_net_num_weights",
+    "ddamg_net_set_weights", "ddamg_net_get_weights", "ddamg_net_add_sample", "ddamg_net_loss_grad",
+    "ddamg_net_train_step", "ddamg_net_propose",
 )
 KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
                 "setup_galerkin", "residual")
@@ -46,6 +50,7 @@ class Params(ctypes.Structure):
         ("coarse_restart", ctypes.c_int32), ("coarse_maxit", ctypes.c_int32),
         ("coarse_fixed_its", ctypes.c_int32), ("outer_restart", ctypes.c_int32),
         ("outer_maxit", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+        ("init_passes", ctypes.c_int32), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -102,6 +107,18 @@ def _load():
         "ddamg_volume": (ctypes.c_int64, [vp]),
         "ddamg_nblocks": (ctypes.c_int32, [vp]),
         "ddamg_set_kernel_timing": (i32, [vp, i32]),
+        "ddamg_set_coarse_host_sync": (i32, [vp, i32]),
+        "ddamg_net_create": (i32, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp, ctypes.POINTER(vp)]),
+        "ddamg_net_destroy": (i32, [vp]),
+        "ddamg_net_last_error": (ctypes.c_char_p, [vp]),
+        "ddamg_net_num_weights": (ctypes.c_int64, [vp]),
+        "ddamg_net_set_weights": (i32, [vp, vp]),
+        "ddamg_net_get_weights": (i32, [vp, vp]),
+        "ddamg_net_add_sample": (i32, [vp, vp, ctypes.POINTER(ctypes.c_int32)]),
+        "ddamg_net_loss_grad": (i32, [vp, ctypes.c_int32, dp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), vp]),
+        "ddamg_net_train_step": (i32, [vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_float,
+                                       ctypes.POINTER(ctypes.c_double)]),
+        "ddamg_net_propose": (i32, [vp, vp, dp, ctypes.c_uint64, dp]),
         "ddamg_get_kernel_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64), i32]),
     }
@@ -219,7 +236,10 @@ class Context:
             pass
 
     # -- the C ABI -----------------------------------------------------------
-    def mg_setup(self, tv_init):
+    def mg_setup(self, tv_init=None):
+        """tv_init None: the library draws the starting vectors from params.seed."""
+        if tv_init is None:
+            return self._check(lib.mg_setup(self.h, None))
         return self._check(lib.mg_setup(self.h, _ptr(tv_init, "tv_init", self.fine_bytes(self.ntv))))
 
     def import_basis(self, W):
@@ -294,6 +314,11 @@ class Context:
     def reset_stats(self):
         return self._check(lib.ddamg_reset_stats(self.h))
 
+    def set_coarse_host_sync(self, each_iteration):
+        """ddamg_set_coarse_host_sync: True makes the host wait for the coarse
+        convergence flags after every coarse iteration (timing comparison)."""
+        return self._check(lib.ddamg_set_coarse_host_sync(self.h, 1 if each_iteration else 0))
+
     def set_kernel_timing(self, on):
         return self._check(lib.ddamg_set_kernel_timing(self.h, 1 if on else 0))
 
@@ -306,3 +331,72 @@ class Context:
         rhs = (ctypes.c_int64 * n)()
         self._check(lib.ddamg_get_kernel_times(self.h, ms, cnt, rhs, n))
         return {k: (ms[i], cnt[i], rhs[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+class Net:
+    """ddamg_net: the gauge-covariant network that proposes test vectors
+    (channels C_0 .. C_L, C_L = ntv), trained on the device.  Weights are a
+    complex64 device tensor, the layers' [C_out][C_in][18] arrays one after
+    the other."""
+
+    def __init__(self, channels, stream=None):
+        import torch
+        self.channels = tuple(int(c) for c in channels)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        arr = (ctypes.c_int32 * len(self.channels))(*self.channels)
+        h = ctypes.c_void_p()
+        rc = lib.ddamg_net_create(arr, len(self.channels) - 1, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise DDAMGError(rc, lib.ddamg_net_last_error(None).decode())
+        self.h = h
+        self.nw = lib.ddamg_net_num_weights(h)
+
+    def _check(self, rc):
+        if rc < 0:
+            raise DDAMGError(rc, lib.ddamg_net_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ddamg_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        return self._check(lib.ddamg_net_set_weights(self.h, _ptr(w, "w", self.nw * 8)))
+
+    def get_weights(self):
+        import torch
+        w = torch.zeros(self.nw, dtype=torch.complex64, device="cuda")
+        self._check(lib.ddamg_net_get_weights(self.h, _ptr(w, "w", self.nw * 8)))
+        return w
+
+    def add_sample(self, ctx):
+        idx = ctypes.c_int32()
+        self._check(lib.ddamg_net_add_sample(self.h, ctx.h, ctypes.byref(idx)))
+        return idx.value
+
+    def loss_grad(self, sample, noise=None, seed=0):
+        """(loss, gradient dL/dRe w + i dL/dIm w as a complex64 tensor)."""
+        import torch
+        g = torch.zeros(self.nw, dtype=torch.complex64, device="cuda")
+        loss = ctypes.c_double()
+        nz = None if noise is None else _ptr(noise, "noise")
+        self._check(lib.ddamg_net_loss_grad(self.h, sample, nz, seed, ctypes.byref(loss), _ptr(g, "grad")))
+        return loss.value, g
+
+    def train_step(self, sample, seed, lr):
+        loss = ctypes.c_double()
+        self._check(lib.ddamg_net_train_step(self.h, sample, seed, lr, ctypes.byref(loss)))
+        return loss.value
+
+    def propose(self, ctx, out, noise=None, seed=0):
+        nz = None if noise is None else _ptr(noise, "noise")
+        return self._check(lib.ddamg_net_propose(self.h, ctx.h, nz, seed, _ptr(out, "out", ctx.fine_bytes(ctx.ntv))))

@@ -219,6 +219,8 @@ struct ddamg_ctx {
   DevBuf nbr;
   DevBuf status;
   int* h_flags = nullptr;        // pinned host mirrors of small device arrays
+  int* h_ring = nullptr;         // [2][64] pinned slots of the pipelined convergence test
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_dbl = nullptr;       // [128]
   cx<double>* h_cx = nullptr;    // [128]
   // canonical <-> internal staging
@@ -258,6 +260,11 @@ struct ddamg_ctx {
   }
   void free_pinned() {
     if (h_flags) (void)hipHostFree(h_flags);
+    if (h_ring) (void)hipHostFree(h_ring);
+    for (auto& e : ring_ev)
+      if (e) (void)hipEventDestroy(e);
+    h_ring = nullptr;
+    ring_ev[0] = ring_ev[1] = nullptr;
     if (h_dbl) (void)hipHostFree(h_dbl);
     if (h_cx) (void)hipHostFree(h_cx);
     h_flags = nullptr;
@@ -282,6 +289,9 @@ struct SolverBase {
   virtual void prolong_canon(double* x, const double* xc, int nrhs) = 0;
   virtual int solve(double* u, const double* f, int nrhs, double tol) = 0;
   virtual void coarse_stats(int& calls, int64_t& its, int& itmax) const = 0;
+  virtual void set_coarse_host_sync(bool each_iteration) = 0;
+  // the aggregate basis (dequantised) in FP32, internal layout [ntv][12][V]
+  virtual void basis_f32(cx<float>* out) = 0;
   virtual void reset_coarse_stats() = 0;
 };
 
@@ -289,7 +299,7 @@ namespace {
 
 // Krylov workspace of one GMRES instance (coarse or outer)
 struct Krylov {
-  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, kdone, h1, h2, n2, part, wscale;
+  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, any, kdone, h1, h2, n2, part, wscale;
   int m = 0, maxr = 0, ldh = 0;
   size_t part_cap = 0;  // entries of part
   ArnoldiState st{};
@@ -306,6 +316,7 @@ struct Krylov {
     inv_h.alloc<double>(maxr);
     abstol.alloc<double>(maxr);
     active.alloc<int>(maxr);
+    any.alloc<int>(1);
     kdone.alloc<int>(maxr);
     h1.alloc<cx<double>>((size_t)maxr * ldh);
     h2.alloc<cx<double>>((size_t)maxr * ldh);
@@ -322,6 +333,7 @@ struct Krylov {
     st.inv_h = inv_h.get<double>();
     st.abstol = abstol.get<double>();
     st.active = active.get<int>();
+    st.any = any.get<int>();
     st.kdone = kdone.get<int>();
     st.m = m;
   }
@@ -364,12 +376,16 @@ struct Solver final : SolverBase {
   int coarse_calls = 0;
   int64_t coarse_its_total = 0;
   int coarse_its_max = 0;
+  // read the coarse convergence flags after every iteration, stalling the
+  // device (the former scheme, kept for the timing comparison)
+  bool sync_each_coarse_it = false;
 
   void coarse_stats(int& calls, int64_t& its, int& itmax) const override {
     calls = coarse_calls;
     its = coarse_its_total;
     itmax = coarse_its_max;
   }
+  void set_coarse_host_sync(bool each_iteration) override { sync_each_coarse_it = each_iteration; }
   void reset_coarse_stats() override {
     coarse_calls = 0;
     coarse_its_total = 0;
@@ -419,20 +435,38 @@ struct Solver final : SolverBase {
   // -------------------------------------------------------- coarse solve
   // S v = D_oo v - D_oe D_ee^{-1} D_eo v on odd compact vectors
   // (v and w: odd-site vectors with rhs strides vstr and wstr)
-  void schur(cx<T>* w, size_t wstr, const cx<T>* v, size_t vstr, int nrhs) {
+  // gate (optional device flag): every kernel returns at once when it is 0
+  void schur(cx<T>* w, size_t wstr, const cx<T>* v, size_t vstr, int nrhs, const int* gate = nullptr) {
     const CoarseView<S> C = cv();
     c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
       launch_coarse_stencil<T, S>(te.get<cx<T>>(), esz(), 0, g.neven, nullptr, 0, nullptr, 0, 0, (T)0, v, vstr,
-                                  g.neven, (T)1, C, g, nrhs, st);
+                                  g.neven, (T)1, C, g, nrhs, st, gate);
     });
     c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
       launch_block_matvec<T>(ue.get<cx<T>>(), esz(), Dinv.get<cx<T>>(), te.get<cx<T>>(), esz(), g.neven, g.nc, nrhs,
-                             st);
+                             st, gate);
     });
     c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
       launch_coarse_stencil<T, S>(w, wstr, g.neven, nodd(), nullptr, 0, v, vstr, g.neven, (T)1, ue.get<cx<T>>(),
-                                  esz(), 0, (T)-1, C, g, nrhs, st);
+                                  esz(), 0, (T)-1, C, g, nrhs, st, gate);
     });
+  }
+
+  // Pipelined convergence test: post(slot) copies the per-rhs active flags
+  // into a pinned host slot behind the work enqueued so far; any_posted(slot)
+  // waits for that copy only.  Posting the flags of iteration k and reading
+  // them after iteration k + 1 is enqueued keeps the device busy while the
+  // host decides; kernels of inactive rhs return at once, so the iteration
+  // enqueued past convergence changes nothing.
+  void post_active(const Krylov& k, int nrhs, int slot) {
+    HIPCK(hipMemcpyAsync(c->h_ring + 64 * slot, k.active.get<int>(), sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCK(hipEventRecord(c->ring_ev[slot], st));
+  }
+  int any_posted(int nrhs, int slot) {
+    HIPCK(hipEventSynchronize(c->ring_ev[slot]));
+    int any = 0;
+    for (int r = 0; r < nrhs; ++r) any |= c->h_ring[64 * slot + r];
+    return any;
   }
 
   int read_any_active(const Krylov& k, int nrhs) {
@@ -497,18 +531,31 @@ struct Solver final : SolverBase {
                 "coarse residual norm");
       launch_arnoldi_start(ck.st, ck.n2.get<cx<double>>(), 1, nrhs, st);
       launch_scale<T, T>(Vb, vsr, Vb, vsr, ck.inv_h.get<double>(), osz(), nrhs, nullptr, st);
-      if (!read_any_active(ck, nrhs)) break;
+      // with a fixed iteration count the schedule is known: no host reads
+      if ((fixed <= 0 || sync_each_coarse_it) && !read_any_active(ck, nrhs)) break;
       int k = 0;
       for (; k < m && its < maxit; ++k) {
         cx<T>* w = Vb + (size_t)(k + 1) * vsj;
-        schur(w, vsr, Vb + (size_t)k * vsj, vsr, nrhs);
+        // every kernel of the iteration is predicated: on the rhs-wise
+        // active flags, and the operator on "some rhs active"
+        schur(w, vsr, Vb + (size_t)k * vsj, vsr, nrhs, ck.any.get<int>());
         c->timed(DDAMG_KERNEL_COARSE_GS, nrhs, [&] { cgs2(ck, Vb, vsj, vsr, k, w, vsr, osz(), nrhs); });
         launch_arnoldi_column(ck.st, k, ck.h1.get<cx<double>>(), ck.h2.get<cx<double>>(), ck.ldh,
                               ck.n2.get<cx<double>>(), 1, nrhs, st);
-        launch_scale<T, T>(w, vsr, w, vsr, ck.inv_h.get<double>(), osz(), nrhs, nullptr, st);
+        launch_scale<T, T>(w, vsr, w, vsr, ck.inv_h.get<double>(), osz(), nrhs, ck.active.get<int>(), st);
         ++its;
-        if (!read_any_active(ck, nrhs)) {
-          ++k;
+        if (sync_each_coarse_it) {
+          if (!read_any_active(ck, nrhs)) {
+            ++k;
+            break;
+          }
+          continue;
+        }
+        if (fixed > 0) continue;
+        post_active(ck, nrhs, k & 1);
+        // iteration k is enqueued: decide on the flags of iteration k - 1
+        if (k >= 1 && !any_posted(nrhs, (k - 1) & 1)) {
+          --its;  // iteration k ran on inactive rhs only
           break;
         }
       }
@@ -616,11 +663,15 @@ struct Solver final : SolverBase {
   void setup(const double* tv_canon) override {
     const int n = g.ntv;
     cx<T>* V = tv.get<cx<T>>();
-    launch_spinor_to_internal<T>(V, reinterpret_cast<const cx<double>*>(tv_canon), g, n, st);
-    // initial setup: smoother with N_smoother = 1, 2, 3 from a zero guess;
-    // the current vectors move to fy (a buffer swap, no copy) and the
-    // result is built in tv
-    for (int k = 1; k <= 3; ++k) {
+    if (tv_canon)
+      launch_spinor_to_internal<T>(V, reinterpret_cast<const cx<double>*>(tv_canon), g, n, st);
+    else
+      launch_gaussian_fields<T>(V, g, n, c->p.seed, st);
+    // initial setup: smoother with N_smoother = 1, 2, 3 from a zero guess
+    // (init_passes = 3, Alg. 4; fewer when the start vectors are already a
+    // proposal); the current vectors move to fy (a buffer swap, no copy) and
+    // the result is built in tv
+    for (int k = 1; k <= c->p.init_passes; ++k) {
       tv.swap(fy);
       V = tv.get<cx<T>>();
       HIPCK(hipMemsetAsync(V, 0, sizeof(cx<T>) * fsz() * n, st));
@@ -646,6 +697,8 @@ struct Solver final : SolverBase {
     launch_copy<T, double>(tv.get<cx<T>>(), fsz(), W, fsz(), fsz(), g.ntv, st);
     build_coarse_from(W);
   }
+
+  void basis_f32(cx<float>* out) override { launch_dequantize_basis<float, S>(out, bv(), g, st); }
 
   void export_basis(double* Wc) override {
     DevBuf Wt;
@@ -939,6 +992,10 @@ int validate(const ddamg_params* p, std::string& why) {
     why = "n_setup, nu and n_mr must be non-negative";
     return DDAMG_EARG;
   }
+  if (p->init_passes < 0 || p->init_passes > 16) {
+    why = "init_passes must be in [0, 16]";
+    return DDAMG_EARG;
+  }
   if (p->coarse_restart < 1 || p->coarse_restart > 64 || p->outer_restart < 1 || p->outer_restart > 64) {
     why = "restart lengths must be in [1, 64]";
     return DDAMG_EARG;
@@ -987,6 +1044,120 @@ void build_tables(ddamg_ctx* c) {
 
 }  // namespace
 
+// ======================================== learned test-vector network
+// A gauge-covariant network (k_learn.hip) that maps random fields to
+// proposed test vectors, with its Adam state and a training set: per sample
+// the FP32 links and the target aggregate basis of a finished setup.
+struct NetSample {
+  DevBuf U;  // FP32 links, internal layout [4][9][V]
+  DevBuf T;  // FP32 target basis, internal layout [ntv][12][V]
+};
+
+// Work buffers of the network on one lattice: the input fields and every
+// layer's pre-gate output, and (training only) gradients and partial sums.
+struct NetWork {
+  Geom g{};
+  bool have = false;
+  DevBuf act, gam0, gam1, lagg, part;
+};
+
+struct ddamg_net {
+  std::vector<int> ch;        // channels C_0 .. C_L
+  std::vector<size_t> woff;   // offset (complex weights) of every layer
+  size_t nw = 0;              // complex weights
+  hipStream_t st = nullptr;
+  std::string err;
+  DevBuf W, Wb, m, v, grad, loss, status;
+  NetWork tw;                 // training (the samples' lattice)
+  NetWork pw;                 // proposals on any lattice
+  std::vector<std::unique_ptr<NetSample>> samples;
+  int64_t step = 0;
+  double* h_loss = nullptr;   // pinned
+  int* h_stat = nullptr;      // pinned
+
+  int nl() const { return (int)ch.size() - 1; }
+  int cmax() const { return *std::max_element(ch.begin(), ch.end()); }
+  // activations: [C_0 input | output of layer 0 | ... | output of layer L-1]
+  cx<float>* act_ptr(NetWork& w, int l) const {
+    size_t o = 0;
+    for (int k = 0; k < l; ++k) o += (size_t)ch[k];
+    return w.act.get<cx<float>>() + o * 12 * (size_t)w.g.V;
+  }
+  cx<float>* wl(int l) { return W.get<cx<float>>() + woff[l]; }
+
+  static bool same_lattice(const Geom& a, const Geom& b) {
+    for (int m = 0; m < 4; ++m)
+      if (a.L[m] != b.L[m] || a.bs[m] != b.bs[m]) return false;
+    return a.ntv == b.ntv;
+  }
+  void ensure(NetWork& w, const Geom& gl, bool training) {
+    if (w.have && same_lattice(w.g, gl)) return;
+    w.g = gl;
+    w.have = true;
+    const size_t V = gl.V;
+    size_t tot = 0;
+    for (int c : ch) tot += (size_t)c;
+    w.act.alloc<cx<float>>(tot * 12 * V);
+    if (!training) return;
+    w.gam0.alloc<cx<float>>((size_t)cmax() * 12 * V);
+    w.gam1.alloc<cx<float>>((size_t)cmax() * 12 * V);
+    w.lagg.alloc<double>((size_t)2 * gl.nblocks);
+    size_t pmax = 0;
+    for (int l = 0; l < nl(); ++l) pmax = std::max(pmax, (size_t)ch[l] * ch[l + 1] * NET_NFEAT);
+    w.part.alloc<cx<double>>((size_t)net_wgrad_chunks(gl) * pmax);
+  }
+  void sync() { HIPCK(hipStreamSynchronize(st)); }
+
+  // forward on links gv: the input (canonical fields, or drawn from seed)
+  // into act(0), every layer's pre-gate output into act(l + 1)
+  void forward(NetWork& w, const GaugeView<float>& gv, const double* noise, uint64_t seed) {
+    if (noise)
+      launch_spinor_to_internal<float>(act_ptr(w, 0), reinterpret_cast<const cx<double>*>(noise), w.g, ch[0], st);
+    else
+      launch_gaussian_fields<float>(act_ptr(w, 0), w.g, ch[0], seed, st);
+    for (int l = 0; l < nl(); ++l)
+      launch_net_layer(act_ptr(w, l + 1), act_ptr(w, l), wl(l), ch[l], ch[l + 1], l > 0, nullptr, gv, w.g, st);
+    check_launch("network forward");
+  }
+
+  // span loss against the target of sample k and the gradient of every
+  // weight into grad; returns the loss
+  double loss_grad(int k, const double* noise, uint64_t seed) {
+    NetSample& smp = *samples[k];
+    NetWork& w = tw;
+    const GaugeView<float> gv{smp.U.get<cx<float>>(), nullptr, nullptr, nullptr};
+    forward(w, gv, noise, seed);
+    const int L = nl();
+    HIPCK(hipMemsetAsync(status.get<int>(), 0, sizeof(int), st));
+    cx<float>* gcur = w.gam0.get<cx<float>>();
+    cx<float>* gnext = w.gam1.get<cx<float>>();
+    launch_net_span_loss(gcur, w.lagg.get<double>(), loss.get<double>(), act_ptr(w, L), smp.T.get<cx<float>>(), w.g,
+                         ch[L], status.get<int>(), st);
+    for (int l = L - 1; l >= 0; --l) {
+      cx<float>* gw = grad.get<cx<float>>() + woff[l];
+      launch_net_wgrad(gw, w.part.get<cx<double>>(), act_ptr(w, l), l > 0, gcur, ch[l], ch[l + 1], gv, w.g, st);
+      if (l > 0) {
+        // input gradient: the transposed layer, then back through the gate
+        launch_net_transpose(Wb.get<cx<float>>(), wl(l), ch[l], ch[l + 1], st);
+        launch_net_layer(gnext, gcur, Wb.get<cx<float>>(), ch[l + 1], ch[l], false, act_ptr(w, l), gv, w.g, st);
+        std::swap(gcur, gnext);
+      }
+    }
+    check_launch("network backward");
+    HIPCK(hipMemcpyAsync(h_loss, loss.get<double>(), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(h_stat, status.get<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    sync();
+    if (*h_stat) throw Fail{DDAMG_ENUMERIC, "proposal of rank below N_tv on an aggregate (span loss undefined)"};
+    if (!std::isfinite(*h_loss)) throw Fail{DDAMG_ENUMERIC, "non-finite span loss"};
+    return *h_loss;
+  }
+
+  ~ddamg_net() {
+    if (h_loss) (void)hipHostFree(h_loss);
+    if (h_stat) (void)hipHostFree(h_stat);
+  }
+};
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -1011,6 +1182,8 @@ void ddamg_default_params(ddamg_params* p) {
   p->outer_maxit = 2000;
   p->prec = DDAMG_MIXED16;
   p->max_rhs = 12;
+  p->init_passes = 3;
+  p->seed = 0;
 }
 
 int ddamg_validate_params(const ddamg_params* p, char* msg, size_t msg_len) {
@@ -1062,6 +1235,8 @@ int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg
     for (int mu = 1; mu < 4; ++mu) g.lstr[mu] = g.lstr[mu - 1] * g.bs[mu - 1];
     build_tables(c.get());
     HIPCK(hipHostMalloc((void**)&c->h_flags, 64 * sizeof(int), hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void**)&c->h_ring, 2 * 64 * sizeof(int), hipHostMallocDefault));
+    for (auto& e : c->ring_ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCK(hipHostMalloc((void**)&c->h_dbl, 128 * sizeof(double), hipHostMallocDefault));
     HIPCK(hipHostMalloc((void**)&c->h_cx, 128 * sizeof(cx<double>), hipHostMallocDefault));
     c->status.alloc<int>(1);
@@ -1145,10 +1320,6 @@ static int check_rhs(ddamg_ctx* c, int nrhs) {
 
 int mg_setup(ddamg_ctx* c, const double* tv_init) {
   if (!c) return DDAMG_EARG;
-  if (!tv_init) {
-    c->err = "tv_init is NULL";
-    return DDAMG_EARG;
-  }
   GUARD_BEGIN
   auto t0 = std::chrono::steady_clock::now();
   c->setup_done = false;
@@ -1458,6 +1629,16 @@ int ddamg_reset_stats(ddamg_ctx* c) {
   return DDAMG_OK;
 }
 
+int ddamg_set_coarse_host_sync(ddamg_ctx* c, int each_iteration) {
+  if (!c) return DDAMG_EARG;
+  if (each_iteration != 0 && each_iteration != 1) {
+    c->err = "each_iteration must be 0 or 1";
+    return DDAMG_EARG;
+  }
+  c->sol->set_coarse_host_sync(each_iteration == 1);
+  return DDAMG_OK;
+}
+
 int ddamg_set_kernel_timing(ddamg_ctx* c, int on) {
   if (!c) return DDAMG_EARG;
   GUARD_BEGIN
@@ -1479,6 +1660,186 @@ int ddamg_get_kernel_times(ddamg_ctx* c, double* ms, int64_t* count, int64_t* rh
   }
   return DDAMG_OK;
   GUARD_END
+}
+
+// ------------------------------------------------ learned proposal (C ABI)
+int ddamg_net_create(const int32_t* channels, int32_t nlayers, void* stream, ddamg_net** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return DDAMG_EARG;
+  }
+  *out = nullptr;
+  if (!channels || nlayers < 1 || nlayers > 8) {
+    g_create_error = "channels must be given for 1 to 8 layers";
+    return DDAMG_EARG;
+  }
+  for (int l = 0; l <= nlayers; ++l)
+    if (channels[l] < 1 || channels[l] > 32) {
+      g_create_error = "channel counts must be in [1, 32]";
+      return DDAMG_EARG;
+    }
+  std::unique_ptr<ddamg_net> n(new ddamg_net());
+  try {
+    n->ch.assign(channels, channels + nlayers + 1);
+    n->st = static_cast<hipStream_t>(stream);
+    for (int l = 0; l < nlayers; ++l) {
+      n->woff.push_back(n->nw);
+      n->nw += (size_t)channels[l] * channels[l + 1] * NET_NFEAT;
+    }
+    size_t wbmax = 0;
+    for (int l = 0; l < nlayers; ++l) wbmax = std::max(wbmax, (size_t)channels[l] * channels[l + 1] * NET_NFEAT);
+    n->W.alloc<cx<float>>(n->nw);
+    n->Wb.alloc<cx<float>>(wbmax);
+    n->m.alloc<cx<float>>(n->nw);
+    n->v.alloc<cx<float>>(n->nw);
+    n->grad.alloc<cx<float>>(n->nw);
+    n->loss.alloc<double>(1);
+    n->status.alloc<int>(1);
+    HIPCK(hipMemsetAsync(n->W.p, 0, sizeof(cx<float>) * n->nw, n->st));
+    HIPCK(hipMemsetAsync(n->m.p, 0, sizeof(cx<float>) * n->nw, n->st));
+    HIPCK(hipMemsetAsync(n->v.p, 0, sizeof(cx<float>) * n->nw, n->st));
+    HIPCK(hipHostMalloc((void**)&n->h_loss, sizeof(double), hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void**)&n->h_stat, sizeof(int), hipHostMallocDefault));
+    n->sync();
+  } catch (const Fail& f) {
+    g_create_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return DDAMG_ENOMEM;
+  }
+  *out = n.release();
+  return DDAMG_OK;
+}
+
+int ddamg_net_destroy(ddamg_net* n) {
+  if (!n) return DDAMG_EARG;
+  (void)hipStreamSynchronize(n->st);
+  delete n;
+  return DDAMG_OK;
+}
+
+const char* ddamg_net_last_error(const ddamg_net* n) { return n ? n->err.c_str() : g_create_error.c_str(); }
+
+int64_t ddamg_net_num_weights(const ddamg_net* n) { return n ? (int64_t)n->nw : -1; }
+
+#define NET_GUARD_BEGIN try {
+#define NET_GUARD_END                        \
+  }                                          \
+  catch (const Fail& f) {                    \
+    n->err = f.msg;                          \
+    return f.code;                           \
+  }                                          \
+  catch (const std::exception& e) {          \
+    n->err = e.what();                       \
+    return DDAMG_ENOMEM;                     \
+  }
+
+int ddamg_net_set_weights(ddamg_net* n, const float* w) {
+  if (!n || !w) return DDAMG_EARG;
+  NET_GUARD_BEGIN
+  HIPCK(hipMemcpyAsync(n->W.p, w, sizeof(cx<float>) * n->nw, hipMemcpyDeviceToDevice, n->st));
+  HIPCK(hipMemsetAsync(n->m.p, 0, sizeof(cx<float>) * n->nw, n->st));
+  HIPCK(hipMemsetAsync(n->v.p, 0, sizeof(cx<float>) * n->nw, n->st));
+  n->step = 0;
+  n->sync();
+  return DDAMG_OK;
+  NET_GUARD_END
+}
+
+int ddamg_net_get_weights(ddamg_net* n, float* w) {
+  if (!n || !w) return DDAMG_EARG;
+  NET_GUARD_BEGIN
+  HIPCK(hipMemcpyAsync(w, n->W.p, sizeof(cx<float>) * n->nw, hipMemcpyDeviceToDevice, n->st));
+  n->sync();
+  return DDAMG_OK;
+  NET_GUARD_END
+}
+
+int ddamg_net_add_sample(ddamg_net* n, ddamg_ctx* c, int32_t* index) {
+  if (!n || !c) return DDAMG_EARG;
+  if (!c->setup_done) {
+    n->err = "the lattice context has no aggregate basis yet (mg_setup first)";
+    return DDAMG_ESTATE;
+  }
+  if (c->g.ntv != n->ch.back()) {
+    n->err = "the network's output channels differ from the context's ntv";
+    return DDAMG_EARG;
+  }
+  if (!n->samples.empty() && !ddamg_net::same_lattice(n->tw.g, c->g)) {
+    n->err = "all training samples must be on one lattice and blocking";
+    return DDAMG_EARG;
+  }
+  NET_GUARD_BEGIN
+  n->ensure(n->tw, c->g, true);
+  std::unique_ptr<NetSample> smp(new NetSample());
+  const size_t V = c->g.V;
+  smp->U.alloc<cx<float>>((size_t)36 * V);
+  smp->T.alloc<cx<float>>((size_t)c->g.ntv * 12 * V);
+  HIPCK(hipMemcpyAsync(smp->U.p, c->U32.p, sizeof(cx<float>) * 36 * V, hipMemcpyDeviceToDevice, c->st));
+  c->sol->basis_f32(smp->T.get<cx<float>>());
+  check_launch("network sample");
+  c->sync();
+  n->samples.push_back(std::move(smp));
+  if (index) *index = (int32_t)n->samples.size() - 1;
+  return DDAMG_OK;
+  NET_GUARD_END
+}
+
+int ddamg_net_loss_grad(ddamg_net* n, int32_t sample, const double* noise, uint64_t seed, double* loss, float* grad) {
+  if (!n) return DDAMG_EARG;
+  if (sample < 0 || sample >= (int32_t)n->samples.size()) {
+    n->err = "no such sample";
+    return DDAMG_EARG;
+  }
+  NET_GUARD_BEGIN
+  const double l = n->loss_grad(sample, noise, seed);
+  if (loss) *loss = l;
+  if (grad) {
+    HIPCK(hipMemcpyAsync(grad, n->grad.p, sizeof(cx<float>) * n->nw, hipMemcpyDeviceToDevice, n->st));
+    n->sync();
+  }
+  return DDAMG_OK;
+  NET_GUARD_END
+}
+
+int ddamg_net_train_step(ddamg_net* n, int32_t sample, uint64_t seed, float lr, double* loss) {
+  if (!n) return DDAMG_EARG;
+  if (sample < 0 || sample >= (int32_t)n->samples.size()) {
+    n->err = "no such sample";
+    return DDAMG_EARG;
+  }
+  if (!(lr > 0.f)) {
+    n->err = "lr must be positive";
+    return DDAMG_EARG;
+  }
+  NET_GUARD_BEGIN
+  const double l = n->loss_grad(sample, nullptr, seed);
+  n->step += 1;
+  launch_adam(n->W.get<float>(), n->m.get<float>(), n->v.get<float>(), n->grad.get<float>(), 2 * n->nw, lr, n->step,
+              n->st);
+  check_launch("network Adam step");
+  if (loss) *loss = l;
+  return DDAMG_OK;
+  NET_GUARD_END
+}
+
+int ddamg_net_propose(ddamg_net* n, ddamg_ctx* c, const double* noise, uint64_t seed, double* out) {
+  if (!n || !c || !out) return DDAMG_EARG;
+  NET_GUARD_BEGIN
+  if (c->g.ntv != n->ch.back()) {
+    n->err = "the network's output channels differ from the context's ntv";
+    return DDAMG_EARG;
+  }
+  if (n->st != c->st) HIPCK(hipStreamSynchronize(c->st));
+  n->ensure(n->pw, c->g, false);
+  n->forward(n->pw, c->gv32(), noise, seed);
+  launch_spinor_to_canonical<float>(reinterpret_cast<cx<double>*>(out), n->act_ptr(n->pw, n->nl()), n->pw.g,
+                                    n->ch.back(), n->st);
+  check_launch("network proposal");
+  n->sync();
+  return DDAMG_OK;
+  NET_GUARD_END
 }
 
 int64_t ddamg_volume(const ddamg_ctx* c) { return c ? (int64_t)c->g.V : -1; }

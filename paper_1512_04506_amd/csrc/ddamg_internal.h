@@ -253,6 +253,10 @@ void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& 
 template <typename T>
 void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st);
 void launch_clover_export(cx<double>* out, const cx<double>* A, const Geom& g, hipStream_t st);
+// n complex Gaussian spinor fields (internal layout) from the counter-based
+// generator Philox4x32-10 keyed by seed, element by canonical index
+template <typename T>
+void launch_gaussian_fields(cx<T>* out, const Geom& g, int n, uint64_t seed, hipStream_t st);
 
 // dslash: out[r] = piece of D applied to in[r] (chi_in >= 0 keeps only that
 // chirality of the input; mu selects the direction of the cross variants).
@@ -285,14 +289,16 @@ void launch_prolong(cx<T>* x, size_t xstr, const cx<T>* xc, size_t cstr, const B
 // coarse stencil: for internal output sites [out_first, out_first + nout):
 // out = add + cs * D_self xs + cn * sum_{slot>0} D_slot xn(nbr)
 // vectors are addressed as ptr[r * str + (ci - first) * nc + k].
+// gate (device int, optional): the kernel does nothing when *gate == 0
 template <typename T, typename S>
 void launch_coarse_stencil(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T>* add, size_t astr,
                            const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr,
-                           int xn_first, T cn, const CoarseView<S>& cv, const Geom& g, int nrhs, hipStream_t st);
+                           int xn_first, T cn, const CoarseView<S>& cv, const Geom& g, int nrhs, hipStream_t st,
+                           const int* gate = nullptr);
 // out[k] = M[k] x[k] for dense nc x nc column-major blocks M (k < nsites)
 template <typename T>
 void launch_block_matvec(cx<T>* out, size_t ostr, const cx<T>* M, const cx<T>* x, size_t xstr, int nsites, int nc,
-                         int nrhs, hipStream_t st);
+                         int nrhs, hipStream_t st, const int* gate = nullptr);
 
 // setup kernels
 // tws: workspace of 2 nblocks * QR_TWS_PER_AGG complex doubles (per aggregate the
@@ -326,6 +332,29 @@ template <typename T>
 void launch_coarse_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st);
 template <typename T>
 void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st);
+
+// ---------------------------------------------- learned test-vector network
+// (k_learn.hip) fields FP32 internal [channel][12][V]; layer weights
+// [C_out][C_in][NET_NFEAT] complex
+constexpr int NET_NFEAT = 18;
+constexpr int NET_WGRAD_SPT = 16;  // sites per thread of the weight-gradient kernel
+// out = layer(in); gate_in: in holds pre-gate activations; gate_bwd_pre != NULL:
+// the transposed layer's result passed back through the gate of the
+// channels whose pre-gate activations are gate_bwd_pre
+void launch_net_layer(cx<float>* out, const cx<float>* in, const cx<float>* W, int cin, int cout, bool gate_in,
+                      const cx<float>* gate_bwd_pre, const GaugeView<float>& gv, const Geom& g, hipStream_t st);
+// weights of the transposed layer (C_in x C_out) from W (C_out x C_in)
+void launch_net_transpose(cx<float>* Wb, const cx<float>* W, int cin, int cout, hipStream_t st);
+// chunks of the weight-gradient reduction; part needs chunks * cin * cout * 18 entries
+int net_wgrad_chunks(const Geom& g);
+void launch_net_wgrad(cx<float>* grad, cx<double>* part, const cx<float>* in, bool gate_in, const cx<float>* gam,
+                      int cin, int cout, const GaugeView<float>& gv, const Geom& g, hipStream_t st);
+// span loss (device *loss), per-aggregate terms loss_agg[2 nblocks] and its
+// gradient gam with respect to X; *status = 1 if an aggregate's X^H X is
+// not positive definite
+void launch_net_span_loss(cx<float>* gam, double* loss_agg, double* loss, const cx<float>* X, const cx<float>* T,
+                          const Geom& g, int ntv, int* status, hipStream_t st);
+void launch_adam(float* w, float* m, float* v, const float* grad, size_t n, float lr, int64_t step, hipStream_t st);
 
 // BLAS on block vectors x[r * rstride + i], i < n, r < nrhs.
 // partial dots: part[(r * nvec + j) * nchunk + c]; final h[r * ldh + j].
@@ -378,6 +407,7 @@ struct ArnoldiState {
   double* inv_h;       // [r] 1 / h_{k+1,k} (0 if breakdown or inactive)
   double* abstol;      // [r] stop threshold (< 0: never)
   int* active;         // [r]
+  int* any;            // [1] 1 if some rhs is active (written with active)
   int* kdone;          // [r] iterations done in this cycle
   int m;
 };

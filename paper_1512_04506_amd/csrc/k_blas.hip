@@ -230,65 +230,75 @@ __device__ inline void givens(cx<double> a, cx<double> b, double& c, cx<double>&
   r = nrm * ph;
 }
 
+// active flags of all rhs into *any (one 64-lane wave, nrhs <= 64)
+__device__ inline void publish_any(const ArnoldiState& s, bool act) {
+  const unsigned long long b = __ballot(act);
+  if (threadIdx.x == 0) *s.any = b != 0ull ? 1 : 0;
+}
+
 __global__ void arnoldi_start_kernel(ArnoldiState s, const cx<double>* norm2, int ldn, int nrhs) {
   const int r = threadIdx.x;
-  if (r >= nrhs) return;
-  const int m = s.m;
-  const double beta = sqrt(fmax(norm2[(size_t)r * ldn].r, 0.0));
-  for (int j = 0; j <= m; ++j) s.g[(size_t)r * (m + 1) + j] = mk(0.0, 0.0);
-  s.g[(size_t)r * (m + 1)] = mk(beta, 0.0);
-  const double tol = s.abstol[r];
-  const bool act = tol < 0.0 ? beta > 0.0 : beta > tol;
-  s.active[r] = act ? 1 : 0;
-  s.inv_h[r] = act ? 1.0 / beta : 0.0;
-  s.kdone[r] = 0;
-  s.est[r] = beta;
+  bool act = false;
+  if (r < nrhs) {
+    const int m = s.m;
+    const double beta = sqrt(fmax(norm2[(size_t)r * ldn].r, 0.0));
+    for (int j = 0; j <= m; ++j) s.g[(size_t)r * (m + 1) + j] = mk(0.0, 0.0);
+    s.g[(size_t)r * (m + 1)] = mk(beta, 0.0);
+    const double tol = s.abstol[r];
+    act = tol < 0.0 ? beta > 0.0 : beta > tol;
+    s.active[r] = act ? 1 : 0;
+    s.inv_h[r] = act ? 1.0 / beta : 0.0;
+    s.kdone[r] = 0;
+    s.est[r] = beta;
+  }
+  publish_any(s, act);
 }
 
 __global__ void arnoldi_column_kernel(ArnoldiState s, int k, const cx<double>* h1, const cx<double>* h2, int ldh,
                                       const cx<double>* norm2, int ldn, int nrhs) {
   const int r = threadIdx.x;
-  if (r >= nrhs) return;
-  if (!s.active[r]) {
-    s.inv_h[r] = 0.0;
-    return;
+  bool act = false;
+  if (r < nrhs && !s.active[r]) s.inv_h[r] = 0.0;
+  if (r < nrhs && s.active[r]) {
+    const int m = s.m;
+    cx<double>* H = s.H + (size_t)r * (m + 1) * m + (size_t)k * (m + 1);
+    cx<double>* cs = s.cs + (size_t)r * m;
+    cx<double>* sn = s.sn + (size_t)r * m;
+    cx<double>* g = s.g + (size_t)r * (m + 1);
+    for (int j = 0; j <= k; ++j) {
+      cx<double> v = h1[(size_t)r * ldh + j];
+      if (h2) v = v + h2[(size_t)r * ldh + j];
+      H[j] = v;
+    }
+    const double hn = sqrt(fmax(norm2[(size_t)r * ldn].r, 0.0));
+    H[k + 1] = mk(hn, 0.0);
+    for (int j = 0; j < k; ++j) {
+      const double c = cs[j].r;
+      const cx<double> sj = sn[j];
+      const cx<double> t = c * H[j] + sj * H[j + 1];
+      H[j + 1] = c * H[j + 1] - conj(sj) * H[j];
+      H[j] = t;
+    }
+    double c;
+    cx<double> sv, rr;
+    givens(H[k], H[k + 1], c, sv, rr);
+    cs[k] = mk(c, 0.0);
+    sn[k] = sv;
+    H[k] = rr;
+    H[k + 1] = mk(0.0, 0.0);
+    const cx<double> gk = g[k];
+    g[k + 1] = neg(conj(sv) * gk);
+    g[k] = c * gk;
+    const double est = sqrt(cabs2(g[k + 1]));
+    s.est[r] = est;
+    s.kdone[r] = k + 1;
+    const double tol = s.abstol[r];
+    const bool stop = !(hn > 0.0) || (tol >= 0.0 && est <= tol) || k + 1 >= m;
+    act = !stop;
+    s.active[r] = stop ? 0 : 1;
+    s.inv_h[r] = stop ? 0.0 : 1.0 / hn;
   }
-  const int m = s.m;
-  cx<double>* H = s.H + (size_t)r * (m + 1) * m + (size_t)k * (m + 1);
-  cx<double>* cs = s.cs + (size_t)r * m;
-  cx<double>* sn = s.sn + (size_t)r * m;
-  cx<double>* g = s.g + (size_t)r * (m + 1);
-  for (int j = 0; j <= k; ++j) {
-    cx<double> v = h1[(size_t)r * ldh + j];
-    if (h2) v = v + h2[(size_t)r * ldh + j];
-    H[j] = v;
-  }
-  const double hn = sqrt(fmax(norm2[(size_t)r * ldn].r, 0.0));
-  H[k + 1] = mk(hn, 0.0);
-  for (int j = 0; j < k; ++j) {
-    const double c = cs[j].r;
-    const cx<double> sj = sn[j];
-    const cx<double> t = c * H[j] + sj * H[j + 1];
-    H[j + 1] = c * H[j + 1] - conj(sj) * H[j];
-    H[j] = t;
-  }
-  double c;
-  cx<double> sv, rr;
-  givens(H[k], H[k + 1], c, sv, rr);
-  cs[k] = mk(c, 0.0);
-  sn[k] = sv;
-  H[k] = rr;
-  H[k + 1] = mk(0.0, 0.0);
-  const cx<double> gk = g[k];
-  g[k + 1] = neg(conj(sv) * gk);
-  g[k] = c * gk;
-  const double est = sqrt(cabs2(g[k + 1]));
-  s.est[r] = est;
-  s.kdone[r] = k + 1;
-  const double tol = s.abstol[r];
-  const bool stop = !(hn > 0.0) || (tol >= 0.0 && est <= tol) || k + 1 >= m;
-  s.active[r] = stop ? 0 : 1;
-  s.inv_h[r] = stop ? 0.0 : 1.0 / hn;
+  publish_any(s, act);
 }
 
 __global__ void arnoldi_solve_kernel(ArnoldiState s, int nrhs) {

@@ -429,7 +429,8 @@ __global__ __launch_bounds__(256) void coarse_stencil_kernel(cx<T>* __restrict__
                                                              T cs, const cx<T>* __restrict__ xn, size_t xnstr,
                                                              int xn_first, T cn, CoarseView<S> cv,
                                                              const cx<T>* __restrict__ Dmat, int nc, int CG,
-                                                             int nrhs) {
+                                                             int nrhs, const int* gate) {
+  if (gate && *gate == 0) return;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   cx<T>* xl = reinterpret_cast<cx<T>*>(smem_raw);  // [nc][RB], later [CG][nc][RB]
   const int ci = out_first + blockIdx.x;
@@ -520,7 +521,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(cx<float>* __restrict_
                                                           const cx<float>* __restrict__ xs, size_t xsstr,
                                                           int xs_first, float cs, const cx<float>* __restrict__ xn,
                                                           size_t xnstr, int xn_first, float cn, CoarseView<S> cv,
-                                                          int nc, int nrhs) {
+                                                          int nc, int nrhs, const int* gate) {
+  if (gate && *gate == 0) return;
   const int ci = out_first + blockIdx.x;
   const int r0 = blockIdx.y * CM_RHS;
   const int nr = min(CM_RHS, nrhs - r0);
@@ -808,7 +810,8 @@ namespace {
 template <typename T, typename S>
 void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T>* add, size_t astr,
                     const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr, int xn_first,
-                    T cn, const CoarseView<S>& cv, const cx<T>* Dmat, int nc, int nrhs, hipStream_t st) {
+                    T cn, const CoarseView<S>& cv, const cx<T>* Dmat, int nc, int nrhs, hipStream_t st,
+                    const int* gate) {
   if (nrhs <= 0 || nout <= 0) return;
   // CG column groups of nc / RP row groups (at most 256 threads), fewer if
   // the CG partial sums of RB rhs would not fit 64 KB of LDS
@@ -820,24 +823,24 @@ void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T
   if (nrhs == 1) {
     const int CG = cg_for(1, 2);
     coarse_stencil_kernel<T, S, 1, 2><<<dim3(nout, 1), CG * (nc / 2), (size_t)CG * nc * sizeof(cx<T>), st>>>(
-        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
+        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs, gate);
   } else if (nrhs <= 4) {
     const int CG = cg_for(4, 2);
     coarse_stencil_kernel<T, S, 4, 2><<<dim3(nout, 1), CG * (nc / 2), (size_t)CG * nc * 4 * sizeof(cx<T>), st>>>(
-        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
+        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs, gate);
   } else {
     if constexpr (std::is_same<T, float>::value) {
       // many rhs in FP32: matrix cores (a wave per 16-row tile, at most 4)
       if (!Dmat && nc <= 64) {
         const int tiles = (nc + 15) / 16;
         coarse_mfma_kernel<S><<<dim3(nout, (nrhs + CM_RHS - 1) / CM_RHS), 64 * tiles, 0, st>>>(
-            out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, nc, nrhs);
+            out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, nc, nrhs, gate);
         return;
       }
     }
     const int CG = cg_for(12, 1);
     coarse_stencil_kernel<T, S, 12, 1><<<dim3(nout, (nrhs + 11) / 12), CG * nc, (size_t)CG * nc * 12 * sizeof(cx<T>), st>>>(
-        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs);
+        out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, Dmat, nc, CG, nrhs, gate);
   }
 }
 }  // namespace
@@ -845,16 +848,18 @@ void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T
 template <typename T, typename S>
 void launch_coarse_stencil(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T>* add, size_t astr,
                            const cx<T>* xs, size_t xsstr, int xs_first, T cs, const cx<T>* xn, size_t xnstr,
-                           int xn_first, T cn, const CoarseView<S>& cv, const Geom& g, int nrhs, hipStream_t st) {
+                           int xn_first, T cn, const CoarseView<S>& cv, const Geom& g, int nrhs, hipStream_t st,
+                           const int* gate) {
   stencil_launch<T, S>(out, ostr, out_first, nout, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv,
-                       nullptr, g.nc, nrhs, st);
+                       nullptr, g.nc, nrhs, st, gate);
 }
 
 template <typename T>
 void launch_block_matvec(cx<T>* out, size_t ostr, const cx<T>* M, const cx<T>* x, size_t xstr, int nsites, int nc,
-                         int nrhs, hipStream_t st) {
+                         int nrhs, hipStream_t st, const int* gate) {
   CoarseView<T> none{nullptr, nullptr, nullptr};
-  stencil_launch<T, T>(out, ostr, 0, nsites, nullptr, 0, x, xstr, 0, (T)1, nullptr, 0, 0, (T)0, none, M, nc, nrhs, st);
+  stencil_launch<T, T>(out, ostr, 0, nsites, nullptr, 0, x, xstr, 0, (T)1, nullptr, 0, 0, (T)0, none, M, nc, nrhs, st,
+                       gate);
 }
 
 template <typename T>
@@ -901,7 +906,7 @@ void launch_coarse_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& 
                                      hipStream_t);                                                                   \
   template void launch_coarse_stencil<T, S>(cx<T>*, size_t, int, int, const cx<T>*, size_t, const cx<T>*, size_t,    \
                                             int, T, const cx<T>*, size_t, int, T, const CoarseView<S>&, const Geom&, \
-                                            int, hipStream_t);                                                       \
+                                            int, hipStream_t, const int*);                                           \
   template void launch_quantize_coarse<T, S>(stc_t<S>*, float*, const cx<T>*, const Geom&, hipStream_t);             \
   template void launch_invert_even_blocks<T, S>(cx<T>*, const CoarseView<S>&, const Geom&, int*, hipStream_t);       \
   template void launch_export_coarse<T, S>(cx<double>*, const CoarseView<S>&, const Geom&, hipStream_t);
@@ -912,7 +917,7 @@ INST_TS(float, __half)
 
 #define INST_T(T)                                                                                                   \
   template void launch_block_matvec<T>(cx<T>*, size_t, const cx<T>*, const cx<T>*, size_t, int, int, int,            \
-                                       hipStream_t);                                                                 \
+                                       hipStream_t, const int*);                                                     \
   template void launch_dagger_fill<T>(cx<T>*, const int*, const Geom&, hipStream_t);                                 \
   template void launch_coarse_import<T>(cx<T>*, const cx<double>*, const Geom&, hipStream_t);                        \
   template void launch_coarse_to_internal<T>(cx<T>*, const cx<double>*, const Geom&, int, hipStream_t);              \

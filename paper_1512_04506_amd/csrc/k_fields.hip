@@ -219,6 +219,60 @@ __global__ void spinor_to_canonical_kernel(cx<double>* canon, const cx<T>* in, G
   for (int k = 0; k < 12; ++k) dst[k] = v[k];
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of the
+// two 32 x 32 -> 64-bit products with multipliers 0xD2511F53 and
+// 0xCD9E8D57, the key advanced by the Weyl constants 0x9E3779B9 and
+// 0xBB67AE85 between rounds.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+
+// Complex Gaussian draw for canonical element i (re, im ~ N(0, 1)): the
+// counter (i mod 2^32, i >> 32, 0, 0) under the key (seed mod 2^32,
+// seed >> 32) gives two 53-bit uniforms u1, u2 in [0, 1), and Box-Muller
+// gives sqrt(-2 log(1 - u1)) (cos 2 pi u2, sin 2 pi u2).
+__device__ inline cx<double> philox_gaussian(uint64_t i, uint64_t seed) {
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0u, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double u1 = (double)(c[0] >> 5) * 0x1p-27 + (double)(c[1] >> 6) * 0x1p-53;
+  const double u2 = (double)(c[2] >> 5) * 0x1p-27 + (double)(c[3] >> 6) * 0x1p-53;
+  const double rho = sqrt(-2.0 * log(1.0 - u1));
+  double sn, cs;
+  sincos(2.0 * M_PI * u2, &sn, &cs);
+  return mk(rho * cs, rho * sn);
+}
+
+// n seeded Gaussian spinor fields in the internal layout; the draw of an
+// element depends on its canonical index only, so the same seed gives the
+// same fields whatever the internal order
+template <typename T>
+__global__ void gaussian_fields_kernel(cx<T>* out, Geom g, int n, uint64_t seed) {
+  const size_t V = g.V;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * V) return;
+  const int s = (int)(idx % V);
+  const size_t r = idx / V;
+  int c[4];
+  site_coords(g, s, c);
+  const uint64_t base = ((uint64_t)r * V + (uint64_t)lex_site(g, c)) * 12;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[(r * 12 + k) * V + s] = cvt<T>(philox_gaussian(base + k, seed));
+}
+
 __global__ void clover_export_kernel(cx<double>* out, const cx<double>* A, Geom g) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
@@ -279,6 +333,13 @@ template void launch_spinor_to_internal<double>(cx<double>*, const cx<double>*, 
 template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, const Geom&, int, hipStream_t);
 template void launch_spinor_to_canonical<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
 template void launch_spinor_to_canonical<float>(cx<double>*, const cx<float>*, const Geom&, int, hipStream_t);
+
+template <typename T>
+void launch_gaussian_fields(cx<T>* out, const Geom& g, int n, uint64_t seed, hipStream_t st) {
+  if (n > 0) gaussian_fields_kernel<T><<<nblk((size_t)n * g.V), TPB, 0, st>>>(out, g, n, seed);
+}
+template void launch_gaussian_fields<double>(cx<double>*, const Geom&, int, uint64_t, hipStream_t);
+template void launch_gaussian_fields<float>(cx<float>*, const Geom&, int, uint64_t, hipStream_t);
 
 void launch_clover_export(cx<double>* out, const cx<double>* A, const Geom& g, hipStream_t st) {
   clover_export_kernel<<<nblk(g.V), TPB, 0, st>>>(out, A, g);

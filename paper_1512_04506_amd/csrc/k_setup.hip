@@ -452,5 +452,6 @@ template void launch_dequantize_basis<float, float>(cx<float>*, const BasisView<
 template void launch_dequantize_basis<float, __half>(cx<float>*, const BasisView<__half>&, const Geom&, hipStream_t);
 template void launch_dequantize_basis<double, __half>(cx<double>*, const BasisView<__half>&, const Geom&, hipStream_t);
 template void launch_dequantize_basis<double, float>(cx<double>*, const BasisView<float>&, const Geom&, hipStream_t);
+template void launch_dequantize_basis<float, double>(cx<float>*, const BasisView<double>&, const Geom&, hipStream_t);
 
 }  // namespace ddamg

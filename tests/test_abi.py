@@ -113,3 +113,35 @@ def test_set_allocator_arguments(dd):
 def test_import_rejects_null_and_missing_setup(dd):
     assert dd.lib.ddamg_import_tv(None, None) == -1
     assert dd.lib.ddamg_import_coarse(None, None) == -1
+
+
+def test_params_struct_matches_the_header(dd, tmp_path):
+    """The ctypes mirror of ddamg_params has the C struct's size and field
+    offsets (a C program compiled against the header prints them), and the
+    binding follows the header's ABI version."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    fields = [f for f, _ in dd.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ddamg.h"\nint main(void) {\n'
+                   '  printf("%d %zu\\n", DDAMG_ABI_VERSION, sizeof(ddamg_params));\n' +
+                   "".join('  printf("%%zu\\n", offsetof(ddamg_params, %s));\n' % f for f in fields) +
+                   "  return 0;\n}\n")
+    exe = str(tmp_path / "layout")
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == dd.ABI_VERSION
+    assert int(out[1]) == ctypes.sizeof(dd.Params)
+    for f, off in zip(fields, out[2:]):
+        assert getattr(dd.Params, f).offset == int(off), f
+    assert fields[-1] == "seed" and dd.default_params().seed == 0
+
+
+def test_setup_without_start_vectors_needs_only_a_context(dd):
+    """mg_setup(ctx, NULL) is the seeded start (Philox4x32-10 on the device
+    keyed by params.seed), not an error: with no context it is still
+    refused before any HIP call."""
+    assert dd.lib.mg_setup(None, None) == -1
+    src = open(HEADER).read()
+    assert "tv_init == NULL" in src and "Philox4x32-10" in src

@@ -16,8 +16,8 @@ tests run exactly those shapes on the smallest lattice that holds them,
 and the 16^4 workload (4^4 blocks, N_tv 20, FP32 preconditioner, 8
 Gaussian rhs) through setup and solve, every residual recomputed by the
 oracle's D.  Tolerances are relative to the largest element of the oracle's
-output; the composite ones (V-cycle, setup) are derived in the design notes
-from the measured error of the single operator applies they chain.
+output: the benchmark spec's 1e-12 / 1e-5 / 1e-2 (FP64 / FP32 / FP16 storage) for
+the operator applies and the V-cycle, 1e-11 / 1e-5 / 1e-2 for the setup.
 """
 import sys
 
@@ -38,9 +38,11 @@ FIXED_ITS, COARSE_RESTART = 6, 4  # a restart inside the fixed coarse iterations
 NRHS_MAX = 24
 # operator applies (the benchmark spec): FP64 1e-12, FP32 1e-5, 16-bit storage 1e-2
 TOL_OP = {0: 1e-12, 1: 1e-5, 2: 1e-2}
-# composites: V-cycle and setup chain dozens of applies and inner products
-TOL_VCYCLE = {0: 1e-10, 1: 1e-5, 2: 2e-2}
-TOL_SETUP = {0: 1e-9, 1: 1e-4, 2: 5e-2}
+# composites: V-cycle and setup chain dozens of applies and inner products;
+# measured here 8e-16 / 3.4e-7 / 3.0e-4 (V-cycle) and 1.1e-15 / 3.1e-7 /
+# 8.3e-4 (setup basis), so the benchmark spec's bars hold for them as well
+TOL_VCYCLE = {0: 1e-12, 1: 1e-5, 2: 1e-2}
+TOL_SETUP = {0: 1e-11, 1: 1e-5, 2: 1e-2}
 
 
 def say(*a):
@@ -190,4 +192,33 @@ def test_workload_16x16x16x16_fp32():
         say("16^4: rhs %d oracle residual %.2e (library %.2e), outer its %d" %
             (r, res, st["relres"][r], st["outer_iterations"]))
         assert res <= 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 12, 17])
+def test_benchshape_fp16_stencil_arithmetic(ref, nrhs):
+    """The stencil with D_c stored in FP16 (per-block FP32 scales) against
+    the oracle applying the library's own stored D_c (exported, dequantised)
+    in FP64: this isolates the arithmetic error of the apply from the
+    storage rounding, and it must be at FP32 level (1e-5).  1 and 3 rhs take
+    the vector kernel, 12 and 17 the f16 matrix-core kernel with its
+    two-part split of the input vectors (a full tile of 16 rhs and a ragged
+    one)."""
+    dd = _gpu()
+    ctx = _ctx(dd, ref["U"], 2)
+    ctx.import_basis(dev(ref["W"]))
+    nb, n = ref["blk"].nblocks, 2 * NTV
+    Dc = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
+    ctx.export_coarse(Dc)
+    Dq = host(Dc)
+    xc = synth.gaussian_coarse(nb, NTV, nrhs, 405)
+    # input entries over several orders of magnitude (rhs k scaled by 10^(k-6))
+    xc = xc * (10.0 ** (np.arange(nrhs) - 6.0)).reshape(-1, 1, 1, 1)
+    out = torch.zeros_like(dev(xc))
+    ctx.coarse_apply(out, dev(xc), nrhs)
+    want = coarse.coarse_apply(Dq, coarse.neighbour_table(ref["blk"]), xc.reshape(nrhs, nb, n)).reshape(xc.shape)
+    got = host(out)
+    e = max(rel(got[r], want[r]) for r in range(nrhs))
+    say("bench shape: FP16-stored D_c, %d rhs, arithmetic rel err %.2e (per rhs, worst)" % (nrhs, e))
+    assert e <= 1e-5
     ctx.close()

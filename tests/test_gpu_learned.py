@@ -1,0 +1,166 @@
+"""The learned test-vector proposal on the GPU (ddamg_net, through the C
+ABI) against the oracle: the network's forward pass, the span loss and the
+gradient of every weight, one Adam step, and a short training run whose loss
+falls.  FP32 arithmetic on the device: tolerance 1e-5 relative to the
+largest element (the benchmark spec's FP32 bar) for the proposal and the loss, and
+for the gradients of every layer.
+
+Network 3 -> 5 -> 6 -> 4 channels (three layers, two gates; 5 and 6 leave
+ragged groups of the four output channels a layer thread computes and the
+two a weight-gradient thread computes) on an 8 x 4 x 4 x 4 lattice with
+4 x 2 x 2 x 2 blocks (16 aggregates of 192 rows each).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import sap, coarse, learned
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+L = (8, 4, 4, 4)
+BLOCK = (4, 2, 2, 2)
+CH = (3, 5, 6, 4)
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1512_04506_amd as dd
+    return dd
+
+
+def flat(ws):
+    return np.concatenate([w.reshape(-1) for w in ws]).astype(np.complex64)
+
+
+def split(v, ch):
+    out, o = [], 0
+    for cin, cout in zip(ch[:-1], ch[1:]):
+        n = cout * cin * 18
+        out.append(v[o:o + n].reshape(cout, cin, 18))
+        o += n
+    return out
+
+
+@pytest.fixture(scope="module")
+def case():
+    dd = _gpu()
+    U = synth.su3_field(L, 0.5, 601)
+    blk = sap.Blocking(L, BLOCK)
+    T = coarse.orthonormalise(blk, synth.gaussian_spinors(L, CH[-1], 602))
+    p = dd.default_params(L=L, block=BLOCK, m0=-0.2, csw=1.0, ntv=CH[-1], prec=dd.FP64, max_rhs=4)
+    ctx = dd.Context(p, dev(U))
+    ctx.import_basis(dev(T))
+    # the same weights on both sides: the FP32 values the device holds
+    ws = [w.astype(np.complex64).astype(np.complex128) for w in synth.network_weights(CH, 603)]
+    net = dd.Net(CH)
+    net.set_weights(dev(flat(ws)))
+    k = net.add_sample(ctx)
+    yield dd, U, blk, T, ctx, ws, net, k
+    net.close()
+    ctx.close()
+
+
+def test_net_proposal_matches_oracle(case):
+    dd, U, blk, T, ctx, ws, net, k = case
+    noise = synth.gaussian_spinors(L, CH[0], 604)
+    out = torch.zeros((CH[-1],) + tuple(reversed(L)) + (4, 3), dtype=torch.complex128, device="cuda")
+    net.propose(ctx, out, noise=dev(noise))
+    ref, _ = learned.forward(U, ws, noise)
+    e = rel(host(out), ref)
+    say("net proposal rel err %.2e" % e)
+    assert e <= TOL
+    # input fields drawn on the device from a seed, as the setup draws them
+    seed = 12345
+    net.propose(ctx, out, seed=seed)
+    ref2, _ = learned.forward(U, ws, synth.philox_gaussian_spinors(L, CH[0], seed))
+    e2 = rel(host(out), ref2)
+    say("net proposal (seeded inputs) rel err %.2e" % e2)
+    assert e2 <= TOL
+
+
+def test_net_loss_and_gradients_match_oracle(case):
+    dd, U, blk, T, ctx, ws, net, k = case
+    noise = synth.gaussian_spinors(L, CH[0], 605)
+    loss, g = net.loss_grad(k, noise=dev(noise))
+    lref, gref = learned.loss_and_grad(U, ws, noise, blk, T)
+    say("net loss %.8f oracle %.8f" % (loss, lref))
+    assert abs(loss - lref) <= TOL * abs(lref)
+    gl = split(host(g).astype(np.complex128), CH)
+    for l in range(len(ws)):
+        e = rel(gl[l], gref[l])
+        say("net gradient layer %d rel err %.2e" % (l, e))
+        assert e <= TOL
+
+
+def test_net_adam_step_matches_oracle(case):
+    """One training step (seeded inputs, loss, backward, Adam) against the
+    oracle's gradient and Adam step from the same weights.  The first Adam
+    step moves each real and imaginary part by about lr against the sign of
+    its gradient, so components whose gradient is below the FP32 noise
+    level may take either sign: those are checked to have moved by at most
+    lr."""
+    dd, U, blk, T, ctx, ws, net, k = case
+    net.set_weights(dev(flat(ws)))
+    seed, lr = 77, 1e-3
+    loss = net.train_step(k, seed, lr)
+    noise = synth.philox_gaussian_spinors(L, CH[0], seed)
+    lref, gref = learned.loss_and_grad(U, ws, noise, blk, T)
+    assert abs(loss - lref) <= TOL * abs(lref)
+    m = [np.zeros_like(w) for w in ws]
+    w1, _, _ = learned.adam_step(ws, gref, m, [np.zeros_like(w) for w in ws], 1, lr)
+    got = split(host(net.get_weights()).astype(np.complex128), CH)
+    for l in range(len(ws)):
+        g = gref[l]
+        big = np.abs(g.real) > 1e-3 * np.abs(g).max(), np.abs(g.imag) > 1e-3 * np.abs(g).max()
+        d = got[l] - w1[l]
+        assert np.abs(d.real[big[0]]).max() <= 1e-3 * lr and np.abs(d.imag[big[1]]).max() <= 1e-3 * lr
+        step = got[l] - ws[l]
+        assert np.abs(step.real).max() <= lr * (1 + 1e-3) and np.abs(step.imag).max() <= lr * (1 + 1e-3)
+    net.set_weights(dev(flat(ws)))
+
+
+def test_net_training_lowers_the_loss(case):
+    """Sixty Adam steps on one sample with fresh random inputs each step:
+    the mean loss of the last ten steps is below that of the first ten."""
+    dd, U, blk, T, ctx, ws, net, k = case
+    net.set_weights(dev(flat(ws)))
+    losses = [net.train_step(k, 1000 + i, 3e-3) for i in range(60)]
+    say("net training losses: first %.4f last %.4f" % (np.mean(losses[:10]), np.mean(losses[-10:])))
+    assert np.mean(losses[-10:]) < np.mean(losses[:10])
+    net.set_weights(dev(flat(ws)))
+
+
+def test_net_argument_errors(case):
+    dd, U, blk, T, ctx, ws, net, k = case
+    with pytest.raises(dd.DDAMGError):
+        net.loss_grad(99)
+    with pytest.raises(dd.DDAMGError):
+        net.train_step(k, 1, -1.0)
+    other = dd.Net((3, 5))  # 5 outputs for a context with ntv 4
+    with pytest.raises(dd.DDAMGError):
+        other.add_sample(ctx)
+    other.close()

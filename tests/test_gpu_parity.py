@@ -53,8 +53,10 @@ CASES = {
 TOL = {0: 1e-12, 1: 1e-5, 2: 1e-2}
 
 
-def make_ctx(dd, L, block, eps, m0, ntv, prec, seed=7, **kw):
-    U = synth.su3_field(L, eps, seed)
+def make_ctx(dd, L, block, eps, m0, ntv, prec, gauge_seed=7, **kw):
+    """A context on a seeded gauge field; kw go to the parameters (seed =
+    the key of the setup's own random start vectors)."""
+    U = synth.su3_field(L, eps, gauge_seed)
     p = dd.default_params(L=L, block=block, m0=m0, csw=1.0, ntv=ntv, prec=prec, max_rhs=kw.pop("max_rhs", 4), **kw)
     ctx = dd.Context(p, dev(U))
     return ctx, U
@@ -200,6 +202,7 @@ def test_vcycle_deterministic(case, prec):
     ctx.mg_apply(x, dev(y), 3)
     ref = np.stack([M.vcycle(y[r]) for r in range(3)])
     tol = {0: 1e-10, 1: 1e-5, 2: 2e-2}[prec]
+    say("vcycle %s prec %d: rel err %.2e" % (case, prec, rel(host(x), ref)))
     assert rel(host(x), ref) <= tol
     # a lone right-hand side goes through the one-vector smoother kernel
     x1 = torch.zeros_like(dev(y[2:3]))
@@ -223,6 +226,7 @@ def test_setup_deterministic(prec):
     W = torch.zeros_like(dev(tv))
     ctx.export_basis(W)
     tol = {0: 1e-9, 1: 1e-4, 2: 5e-2}[prec]
+    say("setup prec %d: basis rel err %.2e" % (prec, rel(host(W), M.W)))
     assert rel(host(W), M.W) <= tol
     nb, n = M.blk.nblocks, 2 * ntv
     Dc = torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda")
@@ -543,4 +547,69 @@ def test_rhs_count_rejected_before_any_work():
             assert b"nrhs" in lib.ddamg_last_error(h), name
     torch.cuda.synchronize()
     assert bool((fo == 7.0).all()) and bool((co == 7.0).all())
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_setup_seeded_start(prec):
+    """mg_setup without start vectors draws them on the device from
+    params.seed (Philox4x32-10 and Box-Muller, as the header states); the
+    same vectors drawn on the host by an independent implementation of that
+    generator give the same basis and D_c.  Another seed gives another
+    basis."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    seed = (7 << 32) + 12345
+    say("seeded setup prec", prec)
+    kw = dict(coarse_fixed_its=6, n_setup=1)
+    ctx1, U = make_ctx(dd, L, block, eps, m0, ntv, prec, seed=seed, **kw)
+    ctx1.mg_setup()
+    ctx2, _ = make_ctx(dd, L, block, eps, m0, ntv, prec, **kw)
+    ctx2.mg_setup(dev(synth.philox_gaussian_spinors(L, ntv, seed)))
+    ctx3, _ = make_ctx(dd, L, block, eps, m0, ntv, prec, seed=seed + 1, **kw)
+    ctx3.mg_setup()
+    shp = (ntv,) + tuple(reversed(L)) + (4, 3)
+    W1, W2, W3 = (torch.zeros(shp, dtype=torch.complex128, device="cuda") for _ in range(3))
+    ctx1.export_basis(W1)
+    ctx2.export_basis(W2)
+    ctx3.export_basis(W3)
+    e = rel(host(W1), host(W2))
+    say("seeded setup prec %d: basis rel diff %.2e" % (prec, e))
+    assert e <= {0: 1e-10, 2: 1e-5}[prec]
+    assert rel(host(W3), host(W2)) > 0.1
+    nb, n = ctx1.nblocks, 2 * ntv
+    D1, D2 = (torch.zeros((nb, 9, n, n), dtype=torch.complex128, device="cuda") for _ in range(2))
+    ctx1.export_coarse(D1)
+    ctx2.export_coarse(D2)
+    assert rel(host(D1), host(D2)) <= {0: 1e-10, 2: 1e-5}[prec]
+    for c in (ctx1, ctx2, ctx3):
+        c.close()
+
+
+@pytest.mark.parametrize("restart", [2, 30])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_coarse_pipelined_convergence_test(prec, restart):
+    """The pipelined convergence test of the coarse GMRES (flags read one
+    iteration late, the extra iteration predicated away) gives bitwise the
+    V-cycle of the per-iteration host read, with the same coarse iteration
+    counts, with and without coarse restarts; a tight coarse tolerance
+    makes the coarse solve run several iterations."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["ragged_6x4x4x4"]
+    say("coarse convergence test prec", prec, "restart", restart)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, coarse_tol=1e-4, coarse_restart=restart)
+    blk, W = _basis(L, block, ntv)
+    ctx.import_basis(dev(W))
+    y = dev(synth.gaussian_spinors(L, 3, 47))
+    out = {}
+    for each in (True, False):
+        ctx.set_coarse_host_sync(each)
+        ctx.reset_stats()
+        x = torch.zeros_like(y)
+        ctx.mg_apply(x, y, 3)
+        out[each] = (host(x), ctx.stats())
+    assert np.array_equal(out[True][0], out[False][0])
+    for k in ("coarse_solves", "coarse_iterations", "coarse_iterations_max"):
+        assert out[True][1][k] == out[False][1][k], k
+    assert out[False][1]["coarse_iterations_max"] >= 4
     ctx.close()

@@ -569,6 +569,116 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(cx<float>* __restrict_
   }
 }
 
+// The same stencil for many rhs when D_c is stored in FP16: on the f16
+// matrix cores (v_mfma_f32_16x16x16_f16), which take D_c as it is stored.
+// The FP32 input vectors are split into two FP16 parts per element, x s =
+// hi + lo 2^-11 with hi = f16(x s) and lo = f16((x s - hi) 2^11), where s
+// is a power of two per rhs that brings the largest |coef D_scale x| over
+// the nine neighbour vectors of the workgroup into [1/2, 1): the two
+// products then carry the input to within 2^-22 of its largest element,
+// the FP32 accumulation is exact to FP32 rounding, and the matrix cores
+// are no longer the bound (16 K per instruction instead of 4).  Complex
+// arithmetic in real form: Yr = Ar Xr - Ai Xi, Yi = Ai Xr + Ar Xi, every
+// loaded D_c element feeding eight MFMAs (two parts, four real products).
+// Workgroup = one coarse site and 16 rhs, one wave per 16-row tile; lane
+// layout of the instruction: A[l % 16][4 (l / 16) + i], B[4 (l / 16) + i]
+// [l % 16], D[4 (l / 16) + v][l % 16].
+typedef _Float16 cm_h4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void coarse_mfma16_kernel(cx<float>* __restrict__ out, size_t ostr, int out_first,
+                                                            const cx<float>* __restrict__ add, size_t astr,
+                                                            const cx<float>* __restrict__ xs, size_t xsstr,
+                                                            int xs_first, float cs, const cx<float>* __restrict__ xn,
+                                                            size_t xnstr, int xn_first, float cn,
+                                                            CoarseView<__half> cv, int nc, int nrhs,
+                                                            const int* gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int smax[CM_RHS];
+  const int ci = out_first + blockIdx.x;
+  const int r0 = blockIdx.y * CM_RHS;
+  const int nr = min(CM_RHS, nrhs - r0);
+  const int t = threadIdx.x;
+  const int lane = t & 63, rt = t >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const size_t nn = (size_t)nc * nc;
+  const int s_beg = cs != 0.f ? 0 : 1;
+  const int s_end = cn != 0.f ? 9 : 1;
+  auto slot_vec = [&](int slot) -> const cx<float>* {
+    const int nb = slot == 0 ? ci : cv.nbr[ci * 9 + slot];
+    return slot == 0 ? xs + (size_t)(nb - xs_first) * nc : xn + (size_t)(nb - xn_first) * nc;
+  };
+  auto slot_str = [&](int slot) -> size_t { return slot == 0 ? xsstr : xnstr; };
+  auto slot_coef = [&](int slot) -> float { return (slot == 0 ? cs : cn) * cv.Dsc[ci * 9 + slot]; };
+  // per-rhs largest |coef D_scale x| over the inputs of this workgroup
+  if (t < CM_RHS) smax[t] = 0;
+  __syncthreads();
+  for (int slot = s_beg; slot < s_end; ++slot) {
+    const cx<float>* xv = slot_vec(slot);
+    const size_t xstr = slot_str(slot);
+    const float ca = fabsf(slot_coef(slot));
+    for (int e = t; e < nc * nr; e += blockDim.x) {
+      const int j = e / nc, k = e - j * nc;
+      const cx<float> v = xv[(size_t)(r0 + j) * xstr + k];
+      const float m = ca * fmaxf(fabsf(v.r), fabsf(v.i));
+      atomicMax(&smax[j], __float_as_int(m));  // non-negative floats order as their bit patterns
+    }
+  }
+  __syncthreads();
+  // this lane's rhs (B column li) and its scale
+  const int bj = min(li, nr - 1);
+  int ex = 0;
+  const float mx = __int_as_float(smax[bj]);
+  if (mx > 0.f) (void)frexpf(mx, &ex);
+  const float sc = ldexpf(1.f, -ex);
+  const int arow = min(rt * 16 + li, nc - 1);
+  cm_v4 ar_h = {0.f, 0.f, 0.f, 0.f}, ai_h = ar_h, ar_l = ar_h, ai_l = ar_h;
+  for (int slot = s_beg; slot < s_end; ++slot) {
+    const cx<float>* xv = slot_vec(slot) + (size_t)(r0 + bj) * slot_str(slot);
+    const float coef = slot_coef(slot) * sc;
+    const __half2* Dp = cv.D + ((size_t)ci * 9 + slot) * nn + arow;
+    for (int k0 = 0; k0 < nc; k0 += 16) {
+      cm_h4 a_r, a_i, a_mi, xr_h, xi_h, xr_l, xi_l;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + 4 * lg + i;
+        const bool kin = k < nc;
+        const int kc = kin ? k : nc - 1;
+        const __half2 a = Dp[(size_t)kc * nc];
+        a_r[i] = (_Float16)__low2half(a);
+        a_i[i] = (_Float16)__high2half(a);
+        a_mi[i] = -a_i[i];
+        const cx<float> x = xv[kc];
+        const float br = kin ? coef * x.r : 0.f, bi = kin ? coef * x.i : 0.f;
+        xr_h[i] = (_Float16)br;
+        xi_h[i] = (_Float16)bi;
+        xr_l[i] = (_Float16)((br - (float)xr_h[i]) * 2048.f);
+        xi_l[i] = (_Float16)((bi - (float)xi_h[i]) * 2048.f);
+      }
+      ar_h = __builtin_amdgcn_mfma_f32_16x16x16f16(a_r, xr_h, ar_h, 0, 0, 0);
+      ar_h = __builtin_amdgcn_mfma_f32_16x16x16f16(a_mi, xi_h, ar_h, 0, 0, 0);
+      ai_h = __builtin_amdgcn_mfma_f32_16x16x16f16(a_i, xr_h, ai_h, 0, 0, 0);
+      ai_h = __builtin_amdgcn_mfma_f32_16x16x16f16(a_r, xi_h, ai_h, 0, 0, 0);
+      ar_l = __builtin_amdgcn_mfma_f32_16x16x16f16(a_r, xr_l, ar_l, 0, 0, 0);
+      ar_l = __builtin_amdgcn_mfma_f32_16x16x16f16(a_mi, xi_l, ar_l, 0, 0, 0);
+      ai_l = __builtin_amdgcn_mfma_f32_16x16x16f16(a_i, xr_l, ai_l, 0, 0, 0);
+      ai_l = __builtin_amdgcn_mfma_f32_16x16x16f16(a_r, xi_l, ai_l, 0, 0, 0);
+    }
+  }
+  // lane: rows 4 lg + v of the tile, rhs li
+  const float inv = 1.f / sc;
+  if (li < nr) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rt * 16 + 4 * lg + v;
+      if (row < nc) {
+        cx<float> o = mk((ar_h[v] + ar_l[v] * (1.f / 2048.f)) * inv, (ai_h[v] + ai_l[v] * (1.f / 2048.f)) * inv);
+        if (add) o = o + add[(size_t)(r0 + li) * astr + (size_t)(ci - out_first) * nc + row];
+        out[(size_t)(r0 + li) * ostr + (size_t)(ci - out_first) * nc + row] = o;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ Eq. (dagger) fill
 // backward block of the neighbour j = i + mu:
 //   D[j][2+2mu](row, col) = s_row s_col conj(D[i][1+2mu](col, row)),
@@ -833,8 +943,13 @@ void stencil_launch(cx<T>* out, size_t ostr, int out_first, int nout, const cx<T
       // many rhs in FP32: matrix cores (a wave per 16-row tile, at most 4)
       if (!Dmat && nc <= 64) {
         const int tiles = (nc + 15) / 16;
-        coarse_mfma_kernel<S><<<dim3(nout, (nrhs + CM_RHS - 1) / CM_RHS), 64 * tiles, 0, st>>>(
-            out, ostr, out_first, add, astr, xs, xsstr, xs_first, cs, xn, xnstr, xn_first, cn, cv, nc, nrhs, gate);
+        const dim3 grid(nout, (nrhs + CM_RHS - 1) / CM_RHS);
+        if constexpr (is_half<S>())
+          coarse_mfma16_kernel<<<grid, 64 * tiles, 0, st>>>(out, ostr, out_first, add, astr, xs, xsstr, xs_first,
+                                                            cs, xn, xnstr, xn_first, cn, cv, nc, nrhs, gate);
+        else
+          coarse_mfma_kernel<S><<<grid, 64 * tiles, 0, st>>>(out, ostr, out_first, add, astr, xs, xsstr, xs_first,
+                                                             cs, xn, xnstr, xn_first, cn, cv, nc, nrhs, gate);
         return;
       }
     }

@@ -115,14 +115,11 @@ __device__ inline void hop_spinor(cx<Tc> acc[4][3], const cx<Tc> p[4][3], const 
   reconstruct<MU, FWD, Tc>(acc, u, coef);
 }
 
-// The same hop applied to NR spinors with one load of the link.
-template <int MU, bool FWD, int NR, typename Tc, typename S>
-__device__ inline void hop_spinor_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const GaugeView<S>& gv,
-                                        int slink, size_t V) {
-  cx<Tc> U[3][3];
-  load_link<Tc, S>(U, gv, MU, slink, V);
-  Tc coef = (Tc)-0.5;
-  if constexpr (is_half<S>()) coef *= (Tc)gv.Usc[slink];
+// acc[r] += coef (1 -+ g_mu) [U or U^dag] p[r] for NR spinors and a link
+// already loaded (entries as stored, coef = -1/2 times the link scale)
+template <int MU, bool FWD, int NR, typename Tc>
+__device__ inline void hop_spinor_multi_u(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const cx<Tc> U[3][3],
+                                          Tc coef) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     Half2<Tc> h, u;
@@ -138,6 +135,17 @@ __device__ inline void hop_spinor_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR]
       }
     reconstruct<MU, FWD, Tc>(acc[r], u, coef);
   }
+}
+
+// The same hop applied to NR spinors with one load of the link.
+template <int MU, bool FWD, int NR, typename Tc, typename S>
+__device__ inline void hop_spinor_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const GaugeView<S>& gv,
+                                        int slink, size_t V) {
+  cx<Tc> U[3][3];
+  load_link<Tc, S>(U, gv, MU, slink, V);
+  Tc coef = (Tc)-0.5;
+  if constexpr (is_half<S>()) coef *= (Tc)gv.Usc[slink];
+  hop_spinor_multi_u<MU, FWD, NR, Tc>(acc, p, U, coef);
 }
 
 template <int MU, bool FWD, typename Tin, typename Tc, typename S, bool CHI>
@@ -181,6 +189,35 @@ __device__ inline void clover_apply(cx<Tc> acc[4][3], const cx<Tc> p[4][3], cons
   }
 }
 
+// acc[r] += sc A_h p[r] on chirality h for NR spinors, the 18 stored pairs
+// of A_h already loaded
+template <int NR, typename Tc>
+__device__ inline void clover_half_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const cx<Tc> a[CLOVER_PAIRS],
+                                         int h, Tc sc) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    cx<Tc> v[6], o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = p[r][2 * h + k / 3][k % 3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      o[2 * k] = a[k].r * v[2 * k];
+      o[2 * k + 1] = a[k].i * v[2 * k + 1];
+    }
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) {
+        o[i] = cfma(a[3 + q], v[j], o[i]);
+        o[j] = cfmac(a[3 + q], v[i], o[j]);
+        ++q;
+      }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[r][2 * h + k / 3][k % 3] = acc[r][2 * h + k / 3][k % 3] + sc * o[k];
+  }
+}
+
 // acc[r] += A(x) p[r] for NR spinors with one load of the clover entries
 template <int NR, typename Tc, typename S>
 __device__ inline void clover_apply_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[NR][4][3], const GaugeView<S>& gv,
@@ -193,28 +230,7 @@ __device__ inline void clover_apply_multi(cx<Tc> acc[NR][4][3], const cx<Tc> p[N
     cx<Tc> a[CLOVER_PAIRS];
 #pragma unroll
     for (int e = 0; e < CLOVER_PAIRS; ++e) a[e] = ldc<Tc>(Ah + (size_t)e * V, (unsigned)s);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      cx<Tc> v[6], o[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) v[k] = p[r][2 * h + k / 3][k % 3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        o[2 * k] = a[k].r * v[2 * k];
-        o[2 * k + 1] = a[k].i * v[2 * k + 1];
-      }
-      int q = 0;
-#pragma unroll
-      for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = i + 1; j < 6; ++j) {
-          o[i] = cfma(a[3 + q], v[j], o[i]);
-          o[j] = cfmac(a[3 + q], v[i], o[j]);
-          ++q;
-        }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) acc[r][2 * h + k / 3][k % 3] = acc[r][2 * h + k / 3][k % 3] + sc * o[k];
-    }
+    clover_half_multi<NR, Tc>(acc, p, a, h, sc);
   }
 }
 

@@ -203,6 +203,89 @@ def generated_fields(L, eps, seeds, workers):
         return pool.map(_field_worker, [(L, eps, s) for s in seeds])
 
 
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=float), q))
+
+
+def batched_serving(dd, torch, n=64, seed=401, workers=(1, 2, 4, 8, 16), field_workers=16):
+    """Batched serving of uneven instances: n independent lattices of the
+    uneven-instance recipe (8^4, 8^3 x 16, 12^4 with 2^4 blocks, 16^4; N_tv
+    16; FP32 preconditioner, FP64 outer; one Gaussian rhs each), every
+    context on a stream of its own.  Setup of all instances by the worker
+    pool, then the n solves served with 1, 2, 4, ... workers; the worker
+    count with the highest throughput is the one reported (a one-parameter
+    tuner of the concurrency).  Latency of a solve = its own call time
+    (service); completion = from the start of the batch to its return."""
+    import synth
+    insts = synth.uneven_instances(n, seed)
+    t0 = time.perf_counter()
+    U = generated_fields_for([(i["L"], i["eps"], i["gauge_seed"]) for i in insts], field_workers)
+    f = [synth.gaussian_spinors(i["L"], 1, i["rhs_seed"]) for i in insts]
+    gen_s = time.perf_counter() - t0
+    ctxs, fd, ud = [], [], []
+    for i, u, ff in zip(insts, U, f):
+        p = dd.default_params(L=i["L"], block=i["block"], m0=i["m0"], csw=i["csw"], ntv=i["ntv"], prec=dd.FP32,
+                              max_rhs=1, seed=i["setup_seed"])
+        Ud = torch.from_numpy(u).cuda()
+        torch.cuda.synchronize()
+        ctxs.append(dd.Context(p, Ud, stream=torch.cuda.Stream()))
+        del Ud
+        fd.append(torch.from_numpy(ff).cuda())
+        ud.append(torch.zeros_like(fd[-1]))
+    del U
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, sinfo = dd.batch_setup(ctxs, workers=8)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    if rc != 0:
+        raise RuntimeError("batched setup: rc %d %s" % (rc, sinfo["rc"]))
+    runs = {}
+    ref = None
+    for wk in workers:
+        for x in ud:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = dd.batch_solve(ctxs, ud, fd, 1, 1e-10, workers=wk)
+        span = (time.perf_counter() - t0) * 1e3
+        if rc != 0:
+            raise RuntimeError("batched solve: rc %d %s" % (rc, info["rc"]))
+        sols = [x.cpu() for x in ud]
+        same = None
+        if ref is None:
+            ref = sols
+        else:
+            same = all(torch.equal(a, b) for a, b in zip(ref, sols))
+        svc = [e - b for b, e in zip(info["begin_ms"], info["end_ms"])]
+        runs[wk] = {"makespan_ms": span, "solves_per_s": n / span * 1e3,
+                    "latency_ms_p50": _pct(svc, 50), "latency_ms_p99": _pct(svc, 99),
+                    "completion_ms_p50": _pct(info["end_ms"], 50), "completion_ms_p99": _pct(info["end_ms"], 99),
+                    "solutions_equal_to_1_worker": same}
+        log("batched serving, %d workers: %s" % (wk, json.dumps(runs[wk])))
+    its = [c.stats()["outer_iterations"] for c in ctxs]
+    relres = max(c.stats()["relres"][0] for c in ctxs)
+    for c in ctxs:
+        c.close()
+    best = max(runs, key=lambda k: runs[k]["solves_per_s"])
+    shapes = {}
+    for i in insts:
+        k = "x".join(str(x) for x in i["L"])
+        shapes[k] = shapes.get(k, 0) + 1
+    return {"instances": n, "seed": seed, "shapes": shapes, "ntv": 16, "prec": "FP32 preconditioner, FP64 outer",
+            "nrhs_per_instance": 1, "tol": 1e-10, "input_generation_s": gen_s, "setup_makespan_ms_8_workers": setup_ms,
+            "outer_iterations_min_max": [min(its), max(its)], "relres_max": relres,
+            "by_workers": {str(k): v for k, v in runs.items()}, "best_workers": best,
+            "speedup_best_vs_1_worker": runs[best]["solves_per_s"] / runs[1]["solves_per_s"] if 1 in runs else None}
+
+
+def generated_fields_for(specs, workers):
+    """Seeded gauge fields for (L, eps, seed) triples, in a process pool."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_field_worker, specs)
+
+
 def learned_eval(dd, torch, w, args):
     """The learned test-vector proposal: train the network on the aggregate
     bases of plain setups on generated 16^4 fields (eps 0.5, m0 -0.2, 4^4
@@ -473,6 +556,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coarse-cost", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched serving of 64 uneven instances")
     ap.add_argument("--learned", action="store_true",
                     help="train the test-vector network and compare learned and plain setups (prints its own line)")
     ap.add_argument("--train-fields", type=int, default=32)
@@ -527,6 +612,13 @@ def main():
         coarse_cost["solve_ms_sync_each"] = solve_sync["sync_each"]
         coarse_cost["solve_ms_pipelined"] = solve_sync["pipelined"]
         log("coarse iteration cost:", json.dumps(coarse_cost))
+    batched = None
+    if not args.no_batched:
+        try:
+            batched = batched_serving(dd, torch)
+        except Exception as e:  # reported, the workload's figures stand on their own
+            batched = {"error": str(e)[:300]}
+        torch.cuda.empty_cache()
     fp64 = None
     if not args.no_fp64:
         fp64 = run_path(dd, torch, w, dd.FP64, U_d, tv_d, f_d, max(1, args.steps // 2), args.warmup)
@@ -557,6 +649,7 @@ def main():
         "kernels_isolated": roof,
         "roofline": dominant_roofline(w, mixed["kernel_times"], dd.MIXED16),
         "coarse_iteration_cost": coarse_cost,
+        "batched_uneven": batched,
     }
     line["roofline"]["traffic"] = measured_traffic(line["roofline"]["kernel"], w["name"])
     if fp64:

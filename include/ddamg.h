@@ -282,6 +282,30 @@ int dirac_apply_noalloc(ddamg_ctx* ctx, double* out, const double* in, int nrhs,
  * Results are identical either way. */
 int ddamg_set_coarse_host_sync(ddamg_ctx* ctx, int each_iteration);
 
+/* ---- batched serving of independent instances ------------------------
+ * Many small lattices of uneven sizes, each its own context, served
+ * together: a pool of `workers` host threads (1 <= workers <= 64) takes the
+ * instances in array order, each thread running one instance's call at a
+ * time, so the kernels of up to `workers` instances are in flight at once.
+ * A small lattice fills a few compute units per launch; the instances'
+ * kernels overlap on the GPU only if their contexts were created on
+ * different streams (contexts sharing a stream are still served correctly,
+ * one after the other on that stream).  Each instance gets exactly the
+ * result of the single-instance call (same kernels, same order of work).
+ * ctx[0 .. n-1] must be distinct contexts (a context is not thread-safe).
+ * Per instance: rc[i] its return code; begin_ms[i] and end_ms[i] (either
+ * may be NULL) when its call started and returned, in milliseconds from
+ * the start of the batch.  Returns 0 if every rc is 0, DDAMG_NOT_CONVERGED
+ * if none is negative and one is 1, else the first negative rc in instance
+ * order (its context's ddamg_last_error tells why); argument errors are
+ * returned before any instance starts.  Synchronous. */
+/* mg_setup(ctx[i], NULL) for every instance (seeded starting vectors). */
+int ddamg_batch_setup(ddamg_ctx* const* ctx, int n, int workers, int32_t* rc, double* begin_ms, double* end_ms);
+/* solve(ctx[i], u[i], f[i], nrhs[i], tol, NULL) for every instance; u[i],
+ * f[i] canonical device fields of instance i's lattice. */
+int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const double* const* f, const int32_t* nrhs,
+                      double tol, int workers, int32_t* rc, double* begin_ms, double* end_ms);
+
 /* Per-kernel-class timing for profiling: when enabled, every launch of the
  * classes below is bracketed by HIP events recorded on the context's stream
  * and the elapsed times are summed (the brackets add a few microseconds of

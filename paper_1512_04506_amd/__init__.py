@@ -30,7 +30,7 @@ EXPORTS = (
     "ddamg_import_coarse", "ddamg_set_allocator", "dirac_apply_noalloc", "ddamg_set_coarse_host_sync",
     "ddamg_net_create", "ddamg_net_destroy", "ddamg_net_last_error", "ddamg_net_num_weights",
     "ddamg_net_set_weights", "ddamg_net_get_weights", "ddamg_net_add_sample", "ddamg_net_loss_grad",
-    "ddamg_net_train_step", "ddamg_net_propose",
+    "ddamg_net_train_step", "ddamg_net_propose", "ddamg_batch_setup", "ddamg_batch_solve",
 )
 KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
                 "setup_galerkin", "residual")
@@ -121,6 +121,12 @@ def _load():
         "ddamg_net_propose": (i32, [vp, vp, dp, ctypes.c_uint64, dp]),
         "ddamg_get_kernel_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64), i32]),
+        "ddamg_batch_setup": (i32, [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "ddamg_batch_solve": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_double, i32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -331,6 +337,48 @@ class Context:
         rhs = (ctypes.c_int64 * n)()
         self._check(lib.ddamg_get_kernel_times(self.h, ms, cnt, rhs, n))
         return {k: (ms[i], cnt[i], rhs[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def _batch_result(rc, ctxs, codes, t0, t1):
+    out = {"rc": [int(x) for x in codes], "begin_ms": list(t0), "end_ms": list(t1)}
+    if rc < 0:
+        bad = next((i for i, x in enumerate(codes) if x < 0), None)
+        msg = lib.ddamg_last_error(ctxs[bad].h).decode() if bad is not None else "invalid batch arguments"
+        raise DDAMGError(rc, msg)
+    return rc, out
+
+
+def batch_setup(ctxs, workers=8):
+    """ddamg_batch_setup: mg_setup(ctx, NULL) for every context, `workers`
+    instances at a time.  Returns (code, {"rc", "begin_ms", "end_ms"})."""
+    n = len(ctxs)
+    hs = (ctypes.c_void_p * max(n, 1))(*[c.h.value for c in ctxs])
+    codes = (ctypes.c_int32 * max(n, 1))()
+    t0 = (ctypes.c_double * max(n, 1))()
+    t1 = (ctypes.c_double * max(n, 1))()
+    rc = lib.ddamg_batch_setup(hs, n, workers, codes, t0, t1)
+    return _batch_result(rc, ctxs, codes[:n], t0[:n], t1[:n])
+
+
+def batch_solve(ctxs, us, fs, nrhs, tol=1e-10, workers=8):
+    """ddamg_batch_solve: solve(ctx[i], us[i], fs[i], nrhs[i], tol) for every
+    instance, `workers` at a time.  nrhs: an int or one per instance.
+    Returns (code, {"rc", "begin_ms", "end_ms"}); per-instance statistics
+    come from each context's stats()."""
+    n = len(ctxs)
+    if isinstance(nrhs, int):
+        nrhs = [nrhs] * n
+    if not (len(us) == len(fs) == len(nrhs) == n):
+        raise ValueError("one u, f and nrhs per context")
+    hs = (ctypes.c_void_p * max(n, 1))(*[c.h.value for c in ctxs])
+    up = (ctypes.c_void_p * max(n, 1))(*[_ptr(u, "u", c.fine_bytes(k)).value for u, c, k in zip(us, ctxs, nrhs)])
+    fp = (ctypes.c_void_p * max(n, 1))(*[_ptr(f, "f", c.fine_bytes(k)).value for f, c, k in zip(fs, ctxs, nrhs)])
+    nr = (ctypes.c_int32 * max(n, 1))(*nrhs)
+    codes = (ctypes.c_int32 * max(n, 1))()
+    t0 = (ctypes.c_double * max(n, 1))()
+    t1 = (ctypes.c_double * max(n, 1))()
+    rc = lib.ddamg_batch_solve(hs, n, up, fp, nr, tol, workers, codes, t0, t1)
+    return _batch_result(rc, ctxs, codes[:n], t0[:n], t1[:n])
 
 
 class Net:

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -15,6 +16,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/ddamg.h"
@@ -1159,6 +1162,57 @@ struct ddamg_net {
 };
 
 // ================================================================== C ABI
+namespace {
+// A pool of host threads serving independent instances: each thread takes
+// the next instance index and runs one(i); the calling thread is one of the
+// workers.  If a thread cannot be started, the ones that did (at least the
+// caller) serve every instance.  rc[i] and the times are written by the
+// thread that ran instance i.
+template <typename F>
+int serve_batch(int n, int workers, int32_t* rc, double* begin_ms, double* end_ms, F&& one) {
+  std::atomic<int> next{0};
+  const auto start = std::chrono::steady_clock::now();
+  auto ms = [&] { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - start).count(); };
+  auto work = [&] {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) return;
+      const double a = ms();
+      const int r = one(i);
+      const double b = ms();
+      rc[i] = r;
+      if (begin_ms) begin_ms[i] = a;
+      if (end_ms) end_ms[i] = b;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < std::min(workers, n); ++w) {
+    try {
+      pool.emplace_back(work);
+    } catch (const std::exception&) {
+      break;
+    }
+  }
+  work();
+  for (auto& t : pool) t.join();
+  int first_neg = 0, any_nc = 0;
+  for (int i = 0; i < n; ++i) {
+    if (rc[i] < 0 && first_neg == 0) first_neg = rc[i];
+    if (rc[i] == DDAMG_NOT_CONVERGED) any_nc = 1;
+  }
+  return first_neg ? first_neg : (any_nc ? DDAMG_NOT_CONVERGED : DDAMG_OK);
+}
+
+int check_batch(ddamg_ctx* const* ctx, int n, int workers, const int32_t* rc) {
+  if (!ctx || n < 0 || !rc) return DDAMG_EARG;
+  if (workers < 1 || workers > 64) return DDAMG_EARG;
+  std::unordered_set<const ddamg_ctx*> seen;
+  for (int i = 0; i < n; ++i)
+    if (!ctx[i] || !seen.insert(ctx[i]).second) return DDAMG_EARG;
+  return DDAMG_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void ddamg_default_params(ddamg_params* p) {
@@ -1637,6 +1691,33 @@ int ddamg_set_coarse_host_sync(ddamg_ctx* c, int each_iteration) {
   }
   c->sol->set_coarse_host_sync(each_iteration == 1);
   return DDAMG_OK;
+}
+
+int ddamg_batch_setup(ddamg_ctx* const* ctx, int n, int workers, int32_t* rc, double* begin_ms, double* end_ms) {
+  if (int e = check_batch(ctx, n, workers, rc)) return e;
+  return serve_batch(n, workers, rc, begin_ms, end_ms, [&](int i) { return mg_setup(ctx[i], nullptr); });
+}
+
+int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const double* const* f, const int32_t* nrhs,
+                      double tol, int workers, int32_t* rc, double* begin_ms, double* end_ms) {
+  if (int e = check_batch(ctx, n, workers, rc)) return e;
+  if (n > 0 && (!u || !f || !nrhs)) return DDAMG_EARG;
+  // the per-instance arguments are checked here, before any instance starts
+  for (int i = 0; i < n; ++i) {
+    ddamg_ctx* c = ctx[i];
+    if (!u[i] || !f[i] || u[i] == f[i]) {
+      c->err = "u and f must be distinct non-NULL pointers";
+      return DDAMG_EARG;
+    }
+    if (int e = check_rhs(c, nrhs[i])) return e;
+    if (!(tol > 0.0) || !(tol < 1.0)) {
+      c->err = "tol must be in (0, 1)";
+      return DDAMG_EARG;
+    }
+    if (int e = need_setup(c)) return e;
+  }
+  return serve_batch(n, workers, rc, begin_ms, end_ms,
+                     [&](int i) { return solve(ctx[i], u[i], f[i], nrhs[i], tol, nullptr); });
 }
 
 int ddamg_set_kernel_timing(ddamg_ctx* c, int on) {

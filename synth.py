@@ -157,3 +157,29 @@ def network_weights(channels, seed):
         g = rng.standard_normal((cout, cin, 18, 2)) / np.sqrt(2.0 * 18 * cin)
         out.append(g[..., 0] + 1j * g[..., 1])
     return out
+
+
+# Batched serving of uneven instances: lattice shapes (Lx, Ly, Lz, Lt) and
+# the block shape each one takes (12^4 splits into an even number of blocks
+# only with 2^4 blocks).
+UNEVEN_SHAPES = ((8, 8, 8, 8), (8, 8, 8, 16), (12, 12, 12, 12), (16, 16, 16, 16))
+
+
+def uneven_instances(n, seed):
+    """n independent instances for batched serving: shape uniform over
+    UNEVEN_SHAPES, link disorder eps uniform in [0.3, 0.5], m0 uniform in
+    [-0.2, -0.05], blocks 2^4 for 12^4 and 4^4 otherwise, N_tv = 16, c_sw = 1.
+    Each instance also gets its own seeds for the gauge field, the setup's
+    starting vectors and one Gaussian right-hand side.  Returns a list of
+    dicts; nothing here draws the fields themselves."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = UNEVEN_SHAPES[int(rng.integers(len(UNEVEN_SHAPES)))]
+        eps = float(rng.uniform(0.3, 0.5))
+        m0 = float(rng.uniform(-0.2, -0.05))
+        block = (2, 2, 2, 2) if L[0] == 12 else (4, 4, 4, 4)
+        base = 1000 * seed + 3 * i
+        out.append(dict(index=i, L=L, block=block, eps=eps, m0=m0, csw=1.0, ntv=16,
+                        gauge_seed=base, setup_seed=base + 1, rhs_seed=base + 2))
+    return out

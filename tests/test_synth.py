@@ -38,3 +38,21 @@ def test_philox_gaussians_layout_and_moments():
     assert abs(np.mean(g.real * g.imag)) < 5 / np.sqrt(n)
     # the seed's high word enters the key
     assert not np.array_equal(synth.philox_gaussian_spinors(L, 1, 5), synth.philox_gaussian_spinors(L, 1, 5 + (1 << 32)))
+
+
+def test_uneven_instances_recipe():
+    """The batched-serving recipe: shapes from the four uneven lattices,
+    parameters in their stated ranges, 2^4 blocks exactly for 12^4 (an even
+    number of blocks per direction), deterministic in the seed."""
+    a = synth.uneven_instances(64, 3)
+    b = synth.uneven_instances(64, 3)
+    assert a == b
+    assert synth.uneven_instances(64, 4) != a
+    assert {i["L"] for i in a} == set(synth.UNEVEN_SHAPES)
+    for i in a:
+        assert 0.3 <= i["eps"] <= 0.5 and -0.2 <= i["m0"] <= -0.05 and i["ntv"] == 16
+        assert i["block"] == ((2, 2, 2, 2) if i["L"][0] == 12 else (4, 4, 4, 4))
+        for L, bs in zip(i["L"], i["block"]):
+            assert L % bs == 0 and (L // bs) % 2 == 0
+    seeds = [s for i in a for s in (i["gauge_seed"], i["setup_seed"], i["rhs_seed"])]
+    assert len(set(seeds)) == len(seeds)

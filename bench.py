@@ -286,6 +286,73 @@ def generated_fields_for(specs, workers):
         return pool.map(_field_worker, specs)
 
 
+def _gamma5(torch, X):
+    """gamma5 = diag(-1, -1, 1, 1) on the spin index of canonical fields."""
+    Y = X.clone(memory_format=torch.contiguous_format)
+    Y[..., :2, :] *= -1
+    return Y
+
+
+def _orthonormal_rows(torch, X):
+    """The fields X[i] made orthonormal (Cholesky QR, twice)."""
+    n = X.shape[0]
+    M = X.reshape(n, -1)
+    for _ in range(2):
+        G = torch.matmul(M, M.conj().transpose(0, 1))  # G_ij = <M_j, M_i> = L L^H
+        L = torch.linalg.cholesky(G)
+        M = torch.linalg.solve_triangular(L, M, upper=False)
+    return M.contiguous().reshape(X.shape)
+
+
+def low_modes(dd, torch, w, U_d, nmodes=20, iters=6, seed=11):
+    """nmodes vectors spanning (approximately) the right singular vectors of
+    D with the smallest singular values on the workload's field: block
+    inverse iteration on D^dag D, (D^dag D)^-1 = D^-1 g5 D^-1 g5 (D^dag =
+    g5 D g5), each D^-1 a solve of all nmodes rhs to 1e-8 by the library
+    (its own plain setup, FGMRES(8) to bound the Krylov basis), then
+    Rayleigh-Ritz with D in FP64.  Returns the Ritz vectors (device,
+    canonical) and their singular-value estimates |D v|."""
+    p = dd.default_params(L=w["L"], block=w["block"], m0=w["m0"], csw=1.0, ntv=w["ntv"], prec=dd.MIXED16,
+                          max_rhs=nmodes, outer_restart=8, seed=302)
+    ctx = dd.Context(p, U_d)
+    ctx.mg_setup()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    shape = (nmodes,) + tuple(reversed(w["L"])) + (4, 3)
+    V = torch.randn(shape, dtype=torch.complex128, device="cuda", generator=gen)
+    for _ in range(iters):
+        V = _orthonormal_rows(torch, V)
+        Y = torch.zeros(shape, dtype=torch.complex128, device="cuda")
+        ctx.solve(Y, _gamma5(torch, V), nmodes, 1e-8)
+        X = _gamma5(torch, Y)
+        del Y
+        V = torch.zeros(shape, dtype=torch.complex128, device="cuda")
+        ctx.solve(V, X, nmodes, 1e-8)
+        del X
+    V = _orthonormal_rows(torch, V)
+    W = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    ctx.dirac_apply(W, V, nmodes, dd.FP64)
+    Wm = W.reshape(nmodes, -1)
+    H = torch.matmul(Wm.conj(), Wm.transpose(0, 1))
+    del W, Wm
+    ev, Q = torch.linalg.eigh(H)
+    V = torch.matmul(Q.transpose(0, 1), V.reshape(nmodes, -1)).contiguous().reshape(shape)
+    ctx.close()
+    return V, [float(x) for x in torch.sqrt(ev.clamp(min=0)).cpu()]
+
+
+def low_mode_capture(torch, ctx, V):
+    """|(1 - P R) v| for every (normalised) low mode v: how much of the
+    near-null space the setup's aggregates miss."""
+    n = V.shape[0]
+    yc = torch.empty((ctx.coarse_bytes(n) // 16,), dtype=torch.complex128, device="cuda")
+    X = torch.empty(V.shape, dtype=torch.complex128, device="cuda")
+    ctx.mg_restrict(yc, V, n)
+    ctx.mg_prolong(X, yc, n)
+    d = (V - X).reshape(n, -1).norm(dim=1) / V.reshape(n, -1).norm(dim=1)
+    return [float(x) for x in d.cpu()]
+
+
 def learned_eval(dd, torch, w, args):
     """The learned test-vector proposal: train the network on the aggregate
     bases of plain setups on generated 16^4 fields (eps 0.5, m0 -0.2, 4^4
@@ -332,6 +399,14 @@ def learned_eval(dd, torch, w, args):
     del U, tv
     nrhs = w["nrhs"]
     rows = []
+    modes = None
+    if args.low_modes > 0:
+        t0 = time.perf_counter()
+        modes, sig = low_modes(dd, torch, w, U_d, nmodes=args.low_modes)
+        res["low_modes"] = {"n": args.low_modes, "method": "6 steps of block inverse iteration on D^dag D, "
+                            "Rayleigh-Ritz", "singular_values": sig, "s": time.perf_counter() - t0}
+        log("learned: %d low modes, singular values %.3g .. %.3g" % (args.low_modes, sig[0], sig[-1]))
+        torch.cuda.empty_cache()
     for name, init_passes, n_setup, start in [("plain", 3, 3, "random"), ("learned", 0, 0, "net"),
                                               ("random_short", 0, 0, "random"), ("learned", 0, 1, "net"),
                                               ("random_short", 0, 1, "random"), ("plain_short", 1, 0, "random")]:
@@ -352,6 +427,9 @@ def learned_eval(dd, torch, w, args):
         u = torch.zeros_like(f_d)
         r = {"setup": name, "init_passes": init_passes, "n_setup": n_setup,
              "proposal_ms": min(x[0] for x in setups), "setup_ms": min(x[1] for x in setups)}
+        if modes is not None:
+            cap = low_mode_capture(torch, ctx, modes)
+            r["low_mode_residual"] = {"mean": float(np.mean(cap)), "max": max(cap), "lowest5_mean": float(np.mean(cap[:5]))}
         try:
             solve_ms = []
             for _ in range(2):  # the first solve of a context also grows its Krylov basis
@@ -563,6 +641,8 @@ def main():
     ap.add_argument("--train-fields", type=int, default=32)
     ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--train-lr", type=float, default=2e-3)
+    ap.add_argument("--low-modes", type=int, default=20,
+                    help="low modes of D for the |(1-PR)v| comparison of --learned (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (a multi-GPU run would split "

@@ -71,3 +71,29 @@ def test_committed_traffic_record_is_well_formed():
         assert {"class", "workload", "kernel", "bytes_per_launch", "sources", "sources_sha256"} <= set(r)
         assert r["bytes_per_launch"] > 0 and len(r["sources_sha256"]) == 64
         assert r["workload"] in {w["name"] for w in bench.WORKLOADS.values()}
+
+
+def test_low_mode_helpers():
+    """The host linear algebra of the low-mode comparison: Cholesky QR rows
+    are orthonormal and span the input; gamma5 flips spins 0 and 1 only; the
+    Rayleigh-Ritz vectors built the way low_modes builds them have |A v_k|^2
+    equal to the Ritz values (here with a dense A)."""
+    import torch
+    torch.manual_seed(0)
+    n, shape = 4, (4, 2, 2, 2, 2, 4, 3)
+    V = torch.randn(shape, dtype=torch.complex128) * torch.arange(1, n + 1, dtype=torch.float64).reshape(n, 1, 1, 1,
+                                                                                                       1, 1, 1)
+    Q = bench._orthonormal_rows(torch, V)
+    M = Q.reshape(n, -1)
+    assert (M @ M.conj().T - torch.eye(n)).abs().max() < 1e-12
+    P = V.reshape(n, -1)
+    assert ((P @ M.conj().T) @ M - P).abs().max() < 1e-12 * P.abs().max()
+    g = bench._gamma5(torch, V)
+    assert torch.equal(g[..., :2, :], -V[..., :2, :]) and torch.equal(g[..., 2:, :], V[..., 2:, :])
+    A = torch.randn(M.shape[1], M.shape[1], dtype=torch.complex128)
+    W = (A @ M.T).T
+    ev, Qh = torch.linalg.eigh(torch.matmul(W.conj(), W.transpose(0, 1)))
+    R = torch.matmul(Qh.transpose(0, 1), M)
+    WR = (A @ R.T).T
+    for k in range(n):
+        assert abs(WR[k].norm() ** 2 - ev[k]) < 1e-9 * ev[-1]

@@ -306,6 +306,16 @@ int ddamg_batch_setup(ddamg_ctx* const* ctx, int n, int workers, int32_t* rc, do
 int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const double* const* f, const int32_t* nrhs,
                       double tol, int workers, int32_t* rc, double* begin_ms, double* end_ms);
 
+/* HIP graphs for the coarse GMRES (Alg. 2): on (the default), each coarse
+ * iteration's launches (the Schur-complement stencil, the Gram-Schmidt
+ * passes, the Arnoldi column, the scaling) are captured once per iteration
+ * index and rhs count into a HIP graph on the context's stream and
+ * replayed, one launch call per iteration instead of ten: what bounds the
+ * solve of a small lattice is the host's launch rate.  Results are
+ * identical either way.  Contexts on the null stream, and any context while
+ * kernel timing is on, launch eagerly.  on = 0 launches eagerly always. */
+int ddamg_set_graphs(ddamg_ctx* ctx, int on);
+
 /* Per-kernel-class timing for profiling: when enabled, every launch of the
  * classes below is bracketed by HIP events recorded on the context's stream
  * and the elapsed times are summed (the brackets add a few microseconds of

@@ -30,7 +30,7 @@ EXPORTS = (
     "ddamg_import_coarse", "ddamg_set_allocator", "dirac_apply_noalloc", "ddamg_set_coarse_host_sync",
     "ddamg_net_create", "ddamg_net_destroy", "ddamg_net_last_error", "ddamg_net_num_weights",
     "ddamg_net_set_weights", "ddamg_net_get_weights", "ddamg_net_add_sample", "ddamg_net_loss_grad",
-    "ddamg_net_train_step", "ddamg_net_propose", "ddamg_batch_setup", "ddamg_batch_solve",
+    "ddamg_net_train_step", "ddamg_net_propose", "ddamg_batch_setup", "ddamg_batch_solve", "ddamg_set_graphs",
 )
 KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
                 "setup_galerkin", "residual")
@@ -108,6 +108,7 @@ def _load():
         "ddamg_nblocks": (ctypes.c_int32, [vp]),
         "ddamg_set_kernel_timing": (i32, [vp, i32]),
         "ddamg_set_coarse_host_sync": (i32, [vp, i32]),
+        "ddamg_set_graphs": (i32, [vp, i32]),
         "ddamg_net_create": (i32, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp, ctypes.POINTER(vp)]),
         "ddamg_net_destroy": (i32, [vp]),
         "ddamg_net_last_error": (ctypes.c_char_p, [vp]),
@@ -324,6 +325,11 @@ class Context:
         """ddamg_set_coarse_host_sync: True makes the host wait for the coarse
         convergence flags after every coarse iteration (timing comparison)."""
         return self._check(lib.ddamg_set_coarse_host_sync(self.h, 1 if each_iteration else 0))
+
+    def set_graphs(self, on):
+        """ddamg_set_graphs: capture and replay each coarse GMRES iteration as
+        a HIP graph (default on; contexts on the null stream stay eager)."""
+        return self._check(lib.ddamg_set_graphs(self.h, 1 if on else 0))
 
     def set_kernel_timing(self, on):
         return self._check(lib.ddamg_set_kernel_timing(self.h, 1 if on else 0))

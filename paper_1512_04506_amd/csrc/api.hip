@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -293,6 +294,7 @@ struct SolverBase {
   virtual int solve(double* u, const double* f, int nrhs, double tol) = 0;
   virtual void coarse_stats(int& calls, int64_t& its, int& itmax) const = 0;
   virtual void set_coarse_host_sync(bool each_iteration) = 0;
+  virtual void set_graphs(bool on) = 0;
   // the aggregate basis (dequantised) in FP32, internal layout [ntv][12][V]
   virtual void basis_f32(cx<float>* out) = 0;
   virtual void reset_coarse_stats() = 0;
@@ -382,6 +384,51 @@ struct Solver final : SolverBase {
   // read the coarse convergence flags after every iteration, stalling the
   // device (the former scheme, kept for the timing comparison)
   bool sync_each_coarse_it = false;
+  // Each coarse GMRES iteration (Schur complement, CGS2, Arnoldi column,
+  // scaling: ten launches) captured once per (iteration index, nrhs) into a
+  // HIP graph and replayed: one launch call instead of ten.  The captured
+  // kernels read only buffers allocated with the solver, so the graphs stay
+  // valid for its lifetime; nothing captured is a memset or a host copy.
+  // Not while kernel timing is on (its events would be captured too).
+  bool use_graphs = true;
+  std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
+  ~Solver() override {
+    for (auto& kv : step_graphs) (void)hipGraphExecDestroy(kv.second);
+  }
+  void set_graphs(bool on) override { use_graphs = on; }
+  template <typename F>
+  void replay_step(int k, int nrhs, F&& enqueue) {
+    // the null stream cannot be captured: contexts on it run eagerly
+    if (!use_graphs || c->kt.on || st == nullptr) {
+      enqueue();
+      return;
+    }
+    auto it = step_graphs.find({k, nrhs});
+    if (it == step_graphs.end()) {
+      // thread-local capture: other contexts may capture on other threads
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        use_graphs = false;  // a stream that cannot be captured: stay eager
+        enqueue();
+        return;
+      }
+      hipGraph_t gr = nullptr;
+      try {
+        enqueue();
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      HIPCK(hipStreamEndCapture(st, &gr));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) throw Fail{DDAMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+      it = step_graphs.emplace(std::make_pair(k, nrhs), ex).first;
+    }
+    HIPCK(hipGraphLaunch(it->second, st));
+  }
 
   void coarse_stats(int& calls, int64_t& its, int& itmax) const override {
     calls = coarse_calls;
@@ -541,11 +588,13 @@ struct Solver final : SolverBase {
         cx<T>* w = Vb + (size_t)(k + 1) * vsj;
         // every kernel of the iteration is predicated: on the rhs-wise
         // active flags, and the operator on "some rhs active"
-        schur(w, vsr, Vb + (size_t)k * vsj, vsr, nrhs, ck.any.get<int>());
-        c->timed(DDAMG_KERNEL_COARSE_GS, nrhs, [&] { cgs2(ck, Vb, vsj, vsr, k, w, vsr, osz(), nrhs); });
-        launch_arnoldi_column(ck.st, k, ck.h1.get<cx<double>>(), ck.h2.get<cx<double>>(), ck.ldh,
-                              ck.n2.get<cx<double>>(), 1, nrhs, st);
-        launch_scale<T, T>(w, vsr, w, vsr, ck.inv_h.get<double>(), osz(), nrhs, ck.active.get<int>(), st);
+        replay_step(k, nrhs, [&] {
+          schur(w, vsr, Vb + (size_t)k * vsj, vsr, nrhs, ck.any.get<int>());
+          c->timed(DDAMG_KERNEL_COARSE_GS, nrhs, [&] { cgs2(ck, Vb, vsj, vsr, k, w, vsr, osz(), nrhs); });
+          launch_arnoldi_column(ck.st, k, ck.h1.get<cx<double>>(), ck.h2.get<cx<double>>(), ck.ldh,
+                                ck.n2.get<cx<double>>(), 1, nrhs, st);
+          launch_scale<T, T>(w, vsr, w, vsr, ck.inv_h.get<double>(), osz(), nrhs, ck.active.get<int>(), st);
+        });
         ++its;
         if (sync_each_coarse_it) {
           if (!read_any_active(ck, nrhs)) {
@@ -1690,6 +1739,16 @@ int ddamg_set_coarse_host_sync(ddamg_ctx* c, int each_iteration) {
     return DDAMG_EARG;
   }
   c->sol->set_coarse_host_sync(each_iteration == 1);
+  return DDAMG_OK;
+}
+
+int ddamg_set_graphs(ddamg_ctx* c, int on) {
+  if (!c) return DDAMG_EARG;
+  if (on != 0 && on != 1) {
+    c->err = "on must be 0 or 1";
+    return DDAMG_EARG;
+  }
+  c->sol->set_graphs(on == 1);
   return DDAMG_OK;
 }
 

@@ -119,17 +119,37 @@ __device__ inline void mix_hop(cx<float> acc[OG][4][3], const cx<float> t[4][3],
   }
 }
 
-template <int MU, int OG, bool GATE>
-__device__ inline void layer_hops(cx<float> acc[OG][4][3], const cx<float>* f, const cx<float>* const w[OG],
-                                  const SitePos& p, const Geom& g, const GaugeView<float>& gv, size_t V) {
-  cx<float> t[4][3], gt[4][3];
-  hop_feature<MU, true, GATE>(t, f, p, g, gv, V);
-  gamma_mul<MU>(gt, t);
-  mix_hop<OG>(acc, t, gt, w, 2 + 2 * (2 * MU));
-  asm volatile("" ::: "memory");
-  hop_feature<MU, false, GATE>(t, f, p, g, gv, V);
-  gamma_mul<MU>(gt, t);
-  mix_hop<OG>(acc, t, gt, w, 2 + 2 * (2 * MU + 1));
+// hop (MU, FWD) of every input channel for the OG outputs: the link, the
+// neighbour index and its boundary sign are loaded once, then each channel's
+// neighbour spinor is transported and mixed in (the link loads dominated the
+// traffic when they were repeated for every input channel)
+template <int MU, bool FWD, int OG, bool GATE>
+__device__ inline void layer_hop_all(cx<float> acc[OG][4][3], const cx<float>* in, int cin,
+                                     const cx<float>* const w0[OG], const SitePos& p, const Geom& g,
+                                     const GaugeView<float>& gv, size_t V) {
+  cx<float> U[3][3];
+  int sn;
+  float sign;
+  if (FWD) {
+    sn = nbr_fwd(g, p, MU);
+    sign = MU == 3 && p.lc[3] == g.bs[3] - 1 && p.bc[3] == g.NB[3] - 1 ? -1.f : 1.f;
+    load_link<float, float>(U, gv, MU, p.S, V);
+  } else {
+    sn = nbr_bwd(g, p, MU);
+    sign = MU == 3 && p.lc[3] == 0 && p.bc[3] == 0 ? -1.f : 1.f;
+    load_link<float, float>(U, gv, MU, sn, V);
+  }
+  const int k = 2 + 2 * (2 * MU + (FWD ? 0 : 1));
+  for (int j = 0; j < cin; ++j) {
+    cx<float> ph[4][3], t[4][3], gt[4][3];
+    load_in<GATE>(ph, in + (size_t)j * 12 * V, sn, V, sign);
+    transport<FWD>(t, ph, U);
+    gamma_mul<MU>(gt, t);
+    const cx<float>* w[OG];
+#pragma unroll
+    for (int q = 0; q < OG; ++q) w[q] = w0[q] + (size_t)j * NFEAT;
+    mix_hop<OG>(acc, t, gt, w, k);
+  }
   asm volatile("" ::: "memory");
 }
 
@@ -156,30 +176,32 @@ __global__ __launch_bounds__(NTPB) void net_layer_kernel(cx<float>* __restrict__
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[q][sp][c] = mk(0.f, 0.f);
+  // weights of the OG outputs for input channel 0; channel j is j * NFEAT on
+  const cx<float>* w0[OG];
+#pragma unroll
+  for (int q = 0; q < OG; ++q) w0[q] = W + (size_t)min(i0 + q, cout - 1) * cin * NFEAT;
   for (int j = 0; j < cin; ++j) {
-    const cx<float>* f = in + (size_t)j * 12 * V;
-    const cx<float>* w[OG];
+    cx<float> ph[4][3];
+    load_in<GATE_IN>(ph, in + (size_t)j * 12 * V, s, V, 1.f);
+    // a phi + b g5 phi, g5 = diag(-1, -1, +1, +1)
 #pragma unroll
-    for (int q = 0; q < OG; ++q) w[q] = W + ((size_t)min(i0 + q, cout - 1) * cin + j) * NFEAT;
-    {
-      cx<float> ph[4][3];
-      load_in<GATE_IN>(ph, f, s, V, 1.f);
-      // a phi + b g5 phi, g5 = diag(-1, -1, +1, +1)
+    for (int q = 0; q < OG; ++q) {
+      const cx<float> a = w0[q][(size_t)j * NFEAT], b = w0[q][(size_t)j * NFEAT + 1];
+      const cx<float> lo = a - b, hi = a + b;
 #pragma unroll
-      for (int q = 0; q < OG; ++q) {
-        const cx<float> a = w[q][0], b = w[q][1];
-        const cx<float> lo = a - b, hi = a + b;
+      for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[q][sp][c] = cfma(sp < 2 ? lo : hi, ph[sp][c], acc[q][sp][c]);
-      }
+        for (int c = 0; c < 3; ++c) acc[q][sp][c] = cfma(sp < 2 ? lo : hi, ph[sp][c], acc[q][sp][c]);
     }
-    layer_hops<0, OG, GATE_IN>(acc, f, w, p, g, gv, V);
-    layer_hops<1, OG, GATE_IN>(acc, f, w, p, g, gv, V);
-    layer_hops<2, OG, GATE_IN>(acc, f, w, p, g, gv, V);
-    layer_hops<3, OG, GATE_IN>(acc, f, w, p, g, gv, V);
   }
+  layer_hop_all<0, true, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<0, false, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<1, true, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<1, false, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<2, true, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<2, false, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<3, true, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
+  layer_hop_all<3, false, OG, GATE_IN>(acc, in, cin, w0, p, g, gv, V);
 #pragma unroll
   for (int q = 0; q < OG; ++q) {
     const int i = i0 + q;

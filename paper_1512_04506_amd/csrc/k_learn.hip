@@ -160,7 +160,7 @@ __device__ inline void layer_hop_all(cx<float> acc[OG][4][3], const cx<float>* i
 // the channels whose pre-gate values are in pre; store instead the gradient
 // with respect to those pre-gate values (the gate's backward).
 template <int OG, bool GATE_IN, bool GATE_BWD>
-__global__ __launch_bounds__(NTPB) void net_layer_kernel(cx<float>* __restrict__ out, const cx<float>* __restrict__ in,
+__global__ __launch_bounds__(NTPB) __attribute__((amdgpu_waves_per_eu(3))) void net_layer_kernel(cx<float>* __restrict__ out, const cx<float>* __restrict__ in,
                                                          const cx<float>* __restrict__ W, int cin, int cout,
                                                          GaugeView<float> gv, Geom g,
                                                          const cx<float>* __restrict__ pre) {

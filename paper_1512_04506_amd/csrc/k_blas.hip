@@ -22,11 +22,14 @@ __device__ inline double wave_sum_d(double v) {
   return v;
 }
 
+// With a single chunk the workgroup's sums are the inner products: they go
+// straight to h (row stride ldh) and no final kernel runs.
 template <typename T>
 __global__ __launch_bounds__(BT) void mdot_partial_kernel(cx<double>* part, const cx<T>* __restrict__ Vb,
                                                           size_t vsj, size_t vsr, int nvec,
                                                           const cx<T>* __restrict__ w, size_t wsr, size_t n,
-                                                          size_t chunk, int nchunk, const int* active) {
+                                                          size_t chunk, int nchunk, const int* active,
+                                                          cx<double>* h, int ldh) {
   __shared__ cx<double> red[MAX_MDOT_VECS][BT / 64];
   const int c = blockIdx.x;
   const int r = blockIdx.y;
@@ -55,7 +58,10 @@ __global__ __launch_bounds__(BT) void mdot_partial_kernel(cx<double>* part, cons
   for (int j = threadIdx.x; j < nvec; j += BT) {
     cx<double> s = mk(0.0, 0.0);
     for (int k = 0; k < BT / 64; ++k) s = s + red[j][k];
-    part[((size_t)r * nvec + j) * nchunk + c] = s;
+    if (nchunk == 1)
+      h[(size_t)r * ldh + j] = s;
+    else
+      part[((size_t)r * nvec + j) * nchunk + c] = s;
   }
 }
 
@@ -106,7 +112,8 @@ template <int MAXV>
 __global__ __launch_bounds__(BT) void gs_fused_kernel(cx<double>* part, const cx<double>* __restrict__ Vb, size_t vsj,
                                                       size_t vsr, int nvec, cx<double>* w, size_t wsr,
                                                       const cx<double>* __restrict__ h, int ldh, size_t n,
-                                                      size_t chunk, int nchunk, const int* active) {
+                                                      size_t chunk, int nchunk, const int* active,
+                                                      cx<double>* h2) {
   __shared__ cx<double> red[MAXV + 1][BT / 64];
   const int c = blockIdx.x;
   const int r = blockIdx.y;
@@ -148,7 +155,10 @@ __global__ __launch_bounds__(BT) void gs_fused_kernel(cx<double>* part, const cx
   for (int j = threadIdx.x; j <= nvec; j += BT) {
     cx<double> sum = mk(0.0, 0.0);
     for (int k = 0; k < BT / 64; ++k) sum = sum + red[j][k];
-    part[((size_t)r * (nvec + 1) + j) * nchunk + c] = sum;
+    if (nchunk == 1)
+      h2[(size_t)r * ldh + j] = sum;  // a single chunk: the sums are final
+    else
+      part[((size_t)r * (nvec + 1) + j) * nchunk + c] = sum;
   }
 }
 
@@ -356,8 +366,8 @@ bool launch_mdot(cx<double>* h, int ldh, cx<double>* part, size_t part_cap, cons
   const int nchunk = blas_nchunks(n);
   const size_t chunk = (n + nchunk - 1) / nchunk;
   mdot_partial_kernel<T><<<dim3(nchunk, nrhs), BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, n, chunk, nchunk,
-                                                            active);
-  mdot_final_kernel<<<dim3(nvec, nrhs), 64, 0, st>>>(h, ldh, part, nvec, nchunk, active);
+                                                            active, h, ldh);
+  if (nchunk > 1) mdot_final_kernel<<<dim3(nvec, nrhs), 64, 0, st>>>(h, ldh, part, nvec, nchunk, active);
   return true;
 }
 
@@ -381,15 +391,15 @@ bool launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap,
   // registers, more waves in flight for this streaming kernel)
   const dim3 grid(nchunk, nrhs);
   if (nvec <= 4)
-    gs_fused_kernel<4><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active);
+    gs_fused_kernel<4><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active, h2);
   else if (nvec <= 8)
-    gs_fused_kernel<8><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active);
+    gs_fused_kernel<8><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active, h2);
   else if (nvec <= 16)
-    gs_fused_kernel<16><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active);
+    gs_fused_kernel<16><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk, active, h2);
   else
     gs_fused_kernel<GS_FUSED_MAXV><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, nvec, w, wsr, h1, ldh, n, chunk, nchunk,
-                                                        active);
-  mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
+                                                        active, h2);
+  if (nchunk > 1) mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
   return true;
 }
 

@@ -325,6 +325,204 @@ __global__ __launch_bounds__(256) void dslash_staged_kernel(cx<Tout>* __restrict
   }
 }
 
+// 4^4 blocks, one rhs, FP32 input and arithmetic: the staged operator with
+// the x and y faces of the neighbour blocks staged in LDS as well.  In the site-major
+// planes a face across x or y is strided (every 4th site, or runs of 4), so
+// each read of it pulls whole lines of the neighbour block; read late in
+// the workgroup's life those lines have left the L2 and are fetched again.
+// Here every lane loads one face site (4 faces x 64 sites = 256 lanes) at
+// the start, next to its own site, while the neighbour workgroups stage the
+// same lines, and keeps only its projection (1 -+ g_mu) psi, the 2-spinor
+// the hop multiplies (half the LDS of the full spinor).  The z and t faces
+// are contiguous runs and stay global.
+constexpr int HB = 4;                 // block extent
+constexpr int HVB = HB * HB * HB * HB;  // sites per block
+constexpr int HF = HVB / HB;          // sites per face
+constexpr int HD = 2;                 // directions whose faces are staged (x, y)
+
+// local index of face site q (the three other coordinates in increasing
+// dimension order) of the face with local coordinate lmu in direction mu
+__device__ inline int face_site(int mu, int lmu, int q) {
+  int c[4], k = 0;
+  for (int d = 0; d < 4; ++d) {
+    if (d == mu) {
+      c[d] = lmu;
+    } else {
+      c[d] = (q >> (2 * k)) & 3;
+      ++k;
+    }
+  }
+  return c[0] + HB * (c[1] + HB * (c[2] + HB * c[3]));
+}
+// face index of local coordinates lc across direction mu
+__device__ inline int face_index(int mu, const int lc[4]) {
+  int q = 0, k = 0;
+  for (int d = 0; d < 4; ++d)
+    if (d != mu) {
+      q |= lc[d] << (2 * k);
+      ++k;
+    }
+  return q;
+}
+
+// acc += -1/2 (1 -+ g_mu) [U or U^dag] psi for a neighbour given by its
+// projected 2-spinor h (the link at slink, as hop_spinor applies it)
+template <int MU, bool FWD, typename Tc, typename S>
+__device__ inline void hop_projected(cx<Tc> acc[4][3], const Half2<Tc>& h, const GaugeView<S>& gv, int slink,
+                                     size_t V) {
+  cx<Tc> U[3][3];
+  load_link<Tc, S>(U, gv, MU, slink, V);
+  Tc coef = (Tc)-0.5;
+  if constexpr (is_half<S>()) coef *= (Tc)gv.Usc[slink];
+  Half2<Tc> u;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<Tc> t = mk((Tc)0, (Tc)0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) t = FWD ? cfma(U[a][b], h.h[sp][b], t) : cfmac(U[b][a], h.h[sp][b], t);
+      u.h[sp][a] = t;
+    }
+  reconstruct<MU, FWD, Tc>(acc, u, coef);
+}
+
+// both hops of direction MU: the neighbour's projected 2-spinor comes from
+// the block in LDS (projected here), from the staged face (x and y), or
+// from global memory (z and t faces, with the time boundary's sign)
+template <int MU, typename Tin, typename Tc, typename S>
+__device__ inline void hops_halo_mu(cx<Tc> acc[4][3], const cx<Tin>* lds, const cx<Tc>* halo, const cx<Tin>* in,
+                                    const GaugeView<S>& gv, const Geom& g, const SitePos& p) {
+  const size_t V = g.V;
+  const int l = p.lc[MU];
+  const bool live = g.V > 0;  // opaque: each hop stays in its own region
+  if (live) {
+    Half2<Tc> h;
+    if (l < HB - 1 || MU >= HD) {
+      cx<Tc> q[4][3];
+      if (l < HB - 1) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q[sp][c] = cvt<Tc>(lds[(3 * sp + c) * HVB + p.l + g.lstr[MU]]);
+      } else {
+        const int sn = nbr_fwd(g, p, MU);
+        const Tc sign = MU == 3 && p.bc[3] == g.NB[3] - 1 ? (Tc)-1 : (Tc)1;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q[sp][c] = sign * cvt<Tc>(elem(in + (size_t)(3 * sp + c) * V, (unsigned)sn));
+      }
+      project<MU, true, Tc>(h, q);
+    } else {
+      const cx<Tc>* hf = halo + (size_t)(2 * MU) * 6 * HF;
+      const int fq = face_index(MU, p.lc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h.h[k / 3][k % 3] = hf[k * HF + fq];
+    }
+    hop_projected<MU, true, Tc, S>(acc, h, gv, p.S, V);
+  }
+  asm volatile("" ::: "memory");
+  if (live) {
+    Half2<Tc> h;
+    const int sb = nbr_bwd(g, p, MU);
+    if (l > 0 || MU >= HD) {
+      cx<Tc> q[4][3];
+      if (l > 0) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q[sp][c] = cvt<Tc>(lds[(3 * sp + c) * HVB + p.l - g.lstr[MU]]);
+      } else {
+        const Tc sign = MU == 3 && p.bc[3] == 0 ? (Tc)-1 : (Tc)1;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q[sp][c] = sign * cvt<Tc>(elem(in + (size_t)(3 * sp + c) * V, (unsigned)sb));
+      }
+      project<MU, false, Tc>(h, q);
+    } else {
+      const cx<Tc>* hf = halo + (size_t)(2 * MU + 1) * 6 * HF;
+      const int fq = face_index(MU, p.lc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h.h[k / 3][k % 3] = hf[k * HF + fq];
+    }
+    hop_projected<MU, false, Tc, S>(acc, h, gv, sb, V);
+  }
+}
+
+template <typename Tin, typename Tout, typename S, typename Tc>
+__global__ __launch_bounds__(HVB) void dslash_halo_kernel(cx<Tout>* __restrict__ out, const cx<Tin>* __restrict__ in,
+                                                          GaugeView<S> gv, Geom g) {
+  __shared__ cx<Tin> lds[12 * HVB];     // the block's spinors [12][256]
+  __shared__ cx<Tc> halo[2 * HD * 6 * HF];  // faces x+, x-, y+, y-: projected 2-spinors [2 HD][6][64]
+  const int bl = xcd_swizzle(blockIdx.x, gridDim.x);  // lexicographic block order
+  int bc[4];
+  bc[0] = bl % g.NB[0];
+  bc[1] = (bl / g.NB[0]) % g.NB[1];
+  bc[2] = (bl / (g.NB[0] * g.NB[1])) % g.NB[2];
+  bc[3] = bl / (g.NB[0] * g.NB[1] * g.NB[2]);
+  const int ci = block_to_int(g, bc);
+  const int l = threadIdx.x;
+  const size_t V = g.V;
+  const int s = ci * HVB + l;
+  // the face site this lane stages: face f = 2 mu + (0 forward, 1 backward),
+  // the neighbour block's sites with local coordinate 0 (forward) or 3
+#pragma unroll
+  for (int k = 0; k < 12; ++k) lds[k * HVB + l] = elem(in + (size_t)k * V, (unsigned)s);
+  if (l < 2 * HD * HF) {
+    const int f = l / HF, q = l % HF, mu = f >> 1;
+    int nc[4] = {bc[0], bc[1], bc[2], bc[3]};
+    if ((f & 1) == 0)
+      nc[mu] = nc[mu] + 1 == g.NB[mu] ? 0 : nc[mu] + 1;
+    else
+      nc[mu] = nc[mu] == 0 ? g.NB[mu] - 1 : nc[mu] - 1;
+    const int sn = block_to_int(g, nc) * HVB + face_site(mu, (f & 1) == 0 ? 0 : HB - 1, q);
+    cx<Tc> ph[4][3];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ph[k / 3][k % 3] = cvt<Tc>(elem(in + (size_t)k * V, (unsigned)sn));
+    // the hop that reads this face site needs only its projection:
+    // (1 - g_mu) for the forward face, (1 + g_mu) for the backward one
+    Half2<Tc> h;
+    if (f == 0)
+      project<0, true, Tc>(h, ph);
+    else if (f == 1)
+      project<0, false, Tc>(h, ph);
+    else if (f == 2)
+      project<1, true, Tc>(h, ph);
+    else
+      project<1, false, Tc>(h, ph);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) halo[(f * 6 + k) * HF + q] = h.h[k / 3][k % 3];
+  }
+  __syncthreads();
+  const SitePos pos = site_pos(g, s);
+  cx<Tc> acc[1][4][3];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[0][sp][k] = mk((Tc)0, (Tc)0);
+  {
+    cx<Tc> p[1][4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) p[0][sp][k] = cvt<Tc>(lds[(3 * sp + k) * HVB + l]);
+    clover_apply_multi<1, Tc, S>(acc, p, gv, s, V);
+  }
+  hops_halo_mu<0, Tin, Tc, S>(acc[0], lds, halo, in, gv, g, pos);
+  asm volatile("" ::: "memory");
+  hops_halo_mu<1, Tin, Tc, S>(acc[0], lds, halo, in, gv, g, pos);
+  asm volatile("" ::: "memory");
+  hops_halo_mu<2, Tin, Tc, S>(acc[0], lds, halo, in, gv, g, pos);
+  asm volatile("" ::: "memory");
+  hops_halo_mu<3, Tin, Tc, S>(acc[0], lds, halo, in, gv, g, pos);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[(size_t)(3 * sp + k) * V + s] = cvt<Tout>(acc[0][sp][k]);
+}
+
 template <typename Tin, typename Tout, typename S, typename Tc, int NR>
 void launch_staged(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, const Geom& g, int nrhs, size_t in_rs,
                    size_t out_rs, hipStream_t st) {
@@ -370,8 +568,16 @@ void launch_dslash(cx<Tout>* out, const cx<Tin>* in, const GaugeView<S>& gv, con
     case DS_FULL:
       // blocks of up to 256 sites: the block-staged kernel, one or two rhs per lane
       if (g.vblock <= 256) {
-        if (nrhs == 1)
+        if (nrhs == 1) {
+          // 4^4 blocks, FP32 input and arithmetic: the x and y faces staged as well
+          if constexpr (sizeof(Tin) == 4 && sizeof(Tc) == 4) {
+            if (g.bs[0] == HB && g.bs[1] == HB && g.bs[2] == HB && g.bs[3] == HB) {
+              dslash_halo_kernel<Tin, Tout, S, Tc><<<g.nblocks, HVB, 0, st>>>(out, in, gv, g);
+              break;
+            }
+          }
           launch_staged<Tin, Tout, S, Tc, 1>(out, in, gv, g, nrhs, in_rstride, out_rstride, st);
+        }
         else
           launch_staged<Tin, Tout, S, Tc, 2>(out, in, gv, g, nrhs, in_rstride, out_rstride, st);
         break;

@@ -222,3 +222,25 @@ def test_benchshape_fp16_stencil_arithmetic(ref, nrhs):
     say("bench shape: FP16-stored D_c, %d rhs, arithmetic rel err %.2e (per rhs, worst)" % (nrhs, e))
     assert e <= 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("Lr", [(8, 8, 8, 8), (8, 8, 8, 16), (16, 8, 8, 8)])
+def test_benchshape_dirac_one_rhs(prec, Lr):
+    """D psi for one rhs on 4^4 blocks against the oracle: with FP32 inputs
+    the kernel that also stages the x and y faces of the neighbour blocks
+    in LDS (two blocks in a direction: both neighbours are the same block;
+    four blocks in x)."""
+    dd = _gpu()
+    U = synth.su3_field(Lr, EPS, 421)
+    A = dirac.clover_term(U, M0, CSW)
+    psi = synth.gaussian_spinors(Lr, 1, 422)
+    want = dirac.apply_D(U, A, psi[0])
+    p = dd.default_params(L=Lr, block=BLOCK, m0=M0, csw=CSW, ntv=NTV, prec=prec, max_rhs=1)
+    ctx = dd.Context(p, dev(U))
+    out = torch.zeros_like(dev(psi))
+    ctx.dirac_apply(out, dev(psi), 1, prec)
+    e = rel(host(out)[0], want)
+    say("one-rhs D on %s, prec %d: rel err %.2e" % (Lr, prec, e))
+    assert e <= TOL_OP[prec]
+    ctx.close()

@@ -638,7 +638,7 @@ def main():
                     help="skip the batched serving of 64 uneven instances")
     ap.add_argument("--learned", action="store_true",
                     help="train the test-vector network and compare learned and plain setups (prints its own line)")
-    ap.add_argument("--train-fields", type=int, default=32)
+    ap.add_argument("--train-fields", type=int, default=256)
     ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--train-lr", type=float, default=2e-3)
     ap.add_argument("--low-modes", type=int, default=20,

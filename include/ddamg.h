@@ -316,6 +316,22 @@ int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const doub
  * kernel timing is on, launch eagerly.  on = 0 launches eagerly always. */
 int ddamg_set_graphs(ddamg_ctx* ctx, int on);
 
+/* Small coarse lattices: at most 64 sites, at most 1.5 MiB of coarse
+ * operator (9 blocks of nc x nc per site in the storage type, e.g. 8^4 with
+ * 4^4 blocks and N_tv = 16 in FP32: 1.2 MiB) and a coarse restart length of
+ * at most 32.  On (the default), the whole coarse solve of Alg. 2 for each
+ * rhs -- the even/odd Schur complement, restarted GMRES with classical
+ * Gram-Schmidt twice, the same Givens rotations and convergence test, the
+ * back substitution and the even sites -- runs in one workgroup in one
+ * launch, instead of about ten launches per GMRES iteration whose latencies
+ * bound the solve of such a lattice.  One workgroup reads the operator at
+ * the L2 bandwidth of one compute unit, hence the byte bound.  Results agree
+ * with the multi-launch solve to rounding (sums in a different order).  Not
+ * used while the host reads the convergence flags after every iteration
+ * (ddamg_set_coarse_host_sync(ctx, 1)).  on = 0: always the multi-launch
+ * solve. */
+int ddamg_set_coarse_single_kernel(ddamg_ctx* ctx, int on);
+
 /* Per-kernel-class timing for profiling: when enabled, every launch of the
  * classes below is bracketed by HIP events recorded on the context's stream
  * and the elapsed times are summed (the brackets add a few microseconds of

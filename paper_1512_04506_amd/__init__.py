@@ -31,6 +31,7 @@ EXPORTS = (
     "ddamg_net_create", "ddamg_net_destroy", "ddamg_net_last_error", "ddamg_net_num_weights",
     "ddamg_net_set_weights", "ddamg_net_get_weights", "ddamg_net_add_sample", "ddamg_net_loss_grad",
     "ddamg_net_train_step", "ddamg_net_propose", "ddamg_batch_setup", "ddamg_batch_solve", "ddamg_set_graphs",
+    "ddamg_set_coarse_single_kernel",
 )
 KERNEL_KINDS = ("sap", "dslash", "restrict", "prolong", "coarse", "coarse_gs", "outer_gs", "setup_qr",
                 "setup_galerkin", "residual")
@@ -109,6 +110,7 @@ def _load():
         "ddamg_set_kernel_timing": (i32, [vp, i32]),
         "ddamg_set_coarse_host_sync": (i32, [vp, i32]),
         "ddamg_set_graphs": (i32, [vp, i32]),
+        "ddamg_set_coarse_single_kernel": (i32, [vp, i32]),
         "ddamg_net_create": (i32, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp, ctypes.POINTER(vp)]),
         "ddamg_net_destroy": (i32, [vp]),
         "ddamg_net_last_error": (ctypes.c_char_p, [vp]),
@@ -330,6 +332,12 @@ class Context:
         """ddamg_set_graphs: capture and replay each coarse GMRES iteration as
         a HIP graph (default on; contexts on the null stream stay eager)."""
         return self._check(lib.ddamg_set_graphs(self.h, 1 if on else 0))
+
+    def set_coarse_single_kernel(self, on):
+        """ddamg_set_coarse_single_kernel: the whole coarse solve in one launch
+        per rhs on coarse lattices of at most 64 sites and 1.5 MiB of coarse
+        operator (default on)."""
+        return self._check(lib.ddamg_set_coarse_single_kernel(self.h, 1 if on else 0))
 
     def set_kernel_timing(self, on):
         return self._check(lib.ddamg_set_kernel_timing(self.h, 1 if on else 0))

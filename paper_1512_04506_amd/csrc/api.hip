@@ -295,6 +295,7 @@ struct SolverBase {
   virtual void coarse_stats(int& calls, int64_t& its, int& itmax) const = 0;
   virtual void set_coarse_host_sync(bool each_iteration) = 0;
   virtual void set_graphs(bool on) = 0;
+  virtual void set_small_coarse(bool on) = 0;
   // the aggregate basis (dequantised) in FP32, internal layout [ntv][12][V]
   virtual void basis_f32(cx<float>* out) = 0;
   virtual void reset_coarse_stats() = 0;
@@ -392,10 +393,22 @@ struct Solver final : SolverBase {
   // Not while kernel timing is on (its events would be captured too).
   bool use_graphs = true;
   std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
+  // coarse lattices of at most COARSE_SMALL_MAX_SITES sites: the whole coarse
+  // solve of a rhs in one workgroup (one launch instead of ten per
+  // iteration); its iteration counts accumulate on the device
+  bool use_small_coarse = true;
+  DevBuf small_its;  // [2] iterations summed, maximum
   ~Solver() override {
     for (auto& kv : step_graphs) (void)hipGraphExecDestroy(kv.second);
   }
   void set_graphs(bool on) override { use_graphs = on; }
+  void set_small_coarse(bool on) override { use_small_coarse = on; }
+  bool small_coarse_applies() const {
+    const size_t op_bytes = (size_t)g.nblocks * 9 * g.nc * g.nc * sizeof(stc_t<S>);
+    return use_small_coarse && g.nblocks <= COARSE_SMALL_MAX_SITES && op_bytes <= COARSE_SMALL_MAX_BYTES &&
+           (size_t)g.nblocks * g.nc <= (size_t)COARSE_SMALL_MAX_VECTOR &&
+           c->p.coarse_restart <= COARSE_SMALL_MAX_RESTART && !sync_each_coarse_it;
+  }
   template <typename F>
   void replay_step(int k, int nrhs, F&& enqueue) {
     // the null stream cannot be captured: contexts on it run eagerly
@@ -434,12 +447,19 @@ struct Solver final : SolverBase {
     calls = coarse_calls;
     its = coarse_its_total;
     itmax = coarse_its_max;
+    int dev[2] = {0, 0};
+    if (hipStreamSynchronize(st) == hipSuccess &&
+        hipMemcpy(dev, small_its.get<int>(), sizeof(dev), hipMemcpyDeviceToHost) == hipSuccess) {
+      its += dev[0];
+      itmax = std::max(itmax, dev[1]);
+    }
   }
   void set_coarse_host_sync(bool each_iteration) override { sync_each_coarse_it = each_iteration; }
   void reset_coarse_stats() override {
     coarse_calls = 0;
     coarse_its_total = 0;
     coarse_its_max = 0;
+    HIPCK(hipMemsetAsync(small_its.get<int>(), 0, 2 * sizeof(int), st));
   }
 
   size_t fsz() const { return (size_t)12 * g.V; }             // fine elements per rhs
@@ -472,6 +492,8 @@ struct Solver final : SolverBase {
     ck.alloc(mc, maxr, std::max(osz(), csz()));
     npart_cap = setup_norm_part_entries(g.ntv, fsz());
     npart.alloc<cx<double>>(npart_cap);
+    small_its.alloc<int>(2);
+    HIPCK(hipMemsetAsync(small_its.get<int>(), 0, 2 * sizeof(int), st));
   }
 
   // ------------------------------------------------------------ smoother
@@ -552,6 +574,16 @@ struct Solver final : SolverBase {
     const int fixed = c->p.coarse_fixed_its;
     const int m = c->p.coarse_restart;
     const int maxit = fixed > 0 ? fixed : c->p.coarse_maxit;
+    if (small_coarse_applies()) {
+      c->timed(DDAMG_KERNEL_COARSE, nrhs, [&] {
+        launch_coarse_gmres_small<T, S>(xcv, ycv, cs_, C, Dinv.get<cx<T>>(), g, te.get<cx<T>>(), ue.get<cx<T>>(),
+                                        bo.get<cx<T>>(), cw.get<cx<T>>(), cV.get<cx<T>>(), (size_t)maxr * osz(),
+                                        m, maxit, fixed > 0 ? -1.0 : c->p.coarse_tol, small_its.get<int>(), nrhs, st);
+      });
+      check_launch("coarse solve");
+      ++coarse_calls;
+      return 0;  // the iterations are counted on the device
+    }
     // ||y_c|| per rhs -> absolute tolerance (computed on the device)
     need_part(launch_mdot<T>(ck.n2.get<cx<double>>(), 1, ck.part.get<cx<double>>(), ck.part_cap, ycv, 0, cs_, 1, ycv,
                              cs_, cs_, nrhs, nullptr, st),
@@ -1749,6 +1781,16 @@ int ddamg_set_graphs(ddamg_ctx* c, int on) {
     return DDAMG_EARG;
   }
   c->sol->set_graphs(on == 1);
+  return DDAMG_OK;
+}
+
+int ddamg_set_coarse_single_kernel(ddamg_ctx* c, int on) {
+  if (!c) return DDAMG_EARG;
+  if (on != 0 && on != 1) {
+    c->err = "on must be 0 or 1";
+    return DDAMG_EARG;
+  }
+  c->sol->set_small_coarse(on == 1);
   return DDAMG_OK;
 }
 

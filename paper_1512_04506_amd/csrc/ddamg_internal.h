@@ -420,5 +420,20 @@ void launch_arnoldi_column(ArnoldiState s, int k, const cx<double>* h1, const cx
                            const cx<double>* norm2, int ldn, int nrhs, hipStream_t st);
 // y = H(1:kd, 1:kd)^{-1} g(1:kd) per rhs (upper triangular)
 void launch_arnoldi_solve(ArnoldiState s, int nrhs, hipStream_t st);
+// the whole coarse solve (Alg. 2) of each rhs in one workgroup, for coarse
+// lattices small enough that launch latency bounds the multi-kernel solve
+// (restart m <= COARSE_SMALL_MAX_RESTART; its_stat[0] += iterations,
+// its_stat[1] = max).
+// One workgroup reads the coarse operator at the L2 bandwidth of one CU, so
+// the path is taken while one stencil pass over the lattice (9 nc x nc
+// blocks per site) stays within COARSE_SMALL_MAX_BYTES.
+constexpr int COARSE_SMALL_MAX_SITES = 64;
+constexpr size_t COARSE_SMALL_MAX_BYTES = (size_t)3 << 19;  // 1.5 MiB
+constexpr int COARSE_SMALL_MAX_RESTART = 32;
+constexpr int COARSE_SMALL_MAX_VECTOR = 1536;  // sites x nc: the LDS copy of a coarse vector
+template <typename T, typename S>
+void launch_coarse_gmres_small(cx<T>* xc, const cx<T>* yc, size_t cstr, const CoarseView<S>& cv, const cx<T>* Dinv,
+                               const Geom& g, cx<T>* te, cx<T>* ue, cx<T>* bo, cx<T>* cw, cx<T>* V, size_t vsj,
+                               int m, int maxit, double tol, int* its_stat, int nrhs, hipStream_t st);
 
 }  // namespace ddamg

@@ -329,6 +329,317 @@ __global__ void arnoldi_solve_kernel(ArnoldiState s, int nrhs) {
   }
 }
 
+// ---------------------------------------------------- small coarse lattices
+// The whole coarse solve of Alg. 2 for one rhs in one workgroup: the
+// even/odd Schur complement S = D_oo - D_oe D_ee^{-1} D_eo, restarted GMRES
+// on S with classical Gram-Schmidt twice, the Givens rotations and the
+// convergence test of arnoldi_start/column_kernel, the back substitution,
+// then x_e = D_ee^{-1} (y_e - D_eo x_o).  For a coarse lattice of a few
+// dozen sites one GMRES iteration is a few microseconds of work; as ten
+// separate launches it is a chain of ten launch latencies, which is what
+// bounds the solve of a small lattice.  Every loop is bounded by maxit or
+// by the restart length m <= SG_M.
+constexpr int SG_T = 512;
+constexpr int SG_M = COARSE_SMALL_MAX_RESTART;
+
+__device__ inline int sg_flag(int* sh, int v) {
+  if (threadIdx.x == 0) *sh = v;
+  __syncthreads();
+  const int r = *sh;
+  __syncthreads();
+  return r;
+}
+
+// One workgroup on one CU streams the coarse operator from L2 once per
+// stencil pass, so the loads in flight set the speed: the neighbour slots
+// (or the columns of a block matvec) are split over G groups of threads that
+// each own one output element, with the inner loop unrolled, and the G
+// partial sums are added in a fixed order through LDS (part: SG_T entries).
+__device__ inline int sg_groups(int nelem, int nsplit) {
+  int G = nelem > 0 ? SG_T / nelem : 1;
+  if (G < 1) G = 1;
+  if (G > nsplit) G = nsplit;
+  return G;
+}
+
+template <typename T>
+__device__ void sg_finish(cx<T>* out, const cx<T>* add, cx<T>* part, int G, int nelem, bool mine, int e,
+                          cx<T> acc) {
+  // G == 1: every thread owns its elements and wrote them already
+  if (G == 1) {
+    __syncthreads();
+    return;
+  }
+  if (mine) part[threadIdx.x] = acc;  // threadIdx.x = q * nelem + e
+  __syncthreads();
+  if (threadIdx.x < nelem) {
+    cx<T> sum = add ? add[e] : mk((T)0, (T)0);
+    for (int q = 0; q < G; ++q) sum = sum + part[q * nelem + e];
+    out[e] = sum;
+  }
+  __syncthreads();
+}
+
+// out[e], e < nsite * nc, for the sites out_first .. out_first + nsite - 1:
+//   add[e] + cs D_self xs(site) + cn sum_{slot > 0} D_slot xn(nbr(slot))
+// The inputs are first copied to xl (LDS, nblocks * nc entries, site-major
+// over the whole lattice): every row of a site reads the same x entries, and
+// as LDS broadcasts they leave the memory pipeline to the operator.  xs holds
+// the out sites, xn the sites of the other parity (all neighbours).
+template <typename T, typename S>
+__device__ void sg_stencil(cx<T>* out, int out_first, int nsite, const cx<T>* add, const cx<T>* xs, int xs_first,
+                           T cs, const cx<T>* xn, int xn_first, T cn, const CoarseView<S>& cv, int nc, int nblocks,
+                           cx<T>* part, cx<T>* xl) {
+  const size_t nn = (size_t)nc * nc;
+  const int nelem = nsite * nc;
+  const int s_beg = cs != (T)0 ? 0 : 1, s_end = cn != (T)0 ? 9 : 1;
+  if (cs != (T)0)
+    for (int e = threadIdx.x; e < nelem; e += SG_T)
+      xl[(size_t)out_first * nc + e] = xs[(size_t)(out_first - xs_first) * nc + e];
+  if (cn != (T)0) {
+    const int nx = xn_first == 0 ? out_first : nblocks - xn_first;
+    for (int e = threadIdx.x; e < nx * nc; e += SG_T) xl[(size_t)xn_first * nc + e] = xn[e];
+  }
+  __syncthreads();
+  const int G = sg_groups(nelem, s_end - s_beg);
+  auto element = [&](int e, int q) {
+    const int ls = e / nc, row = e - ls * nc;
+    const int ci = out_first + ls;
+    cx<T> acc = mk((T)0, (T)0);
+    for (int slot = s_beg + q; slot < s_end; slot += G) {
+      const int nb = slot == 0 ? ci : cv.nbr[ci * 9 + slot];
+      const cx<T>* xv = xl + (size_t)nb * nc;
+      T coef = slot == 0 ? cs : cn;
+      if constexpr (is_half<S>()) coef *= (T)cv.Dsc[ci * 9 + slot];
+      const size_t base = ((size_t)ci * 9 + slot) * nn + row;
+      cx<T> sum = mk((T)0, (T)0);
+#pragma unroll 8
+      for (int k = 0; k < nc; ++k) sum = sum + ldc<T>(cv.D, base + (size_t)k * nc) * xv[k];
+      acc = acc + coef * sum;
+    }
+    return acc;
+  };
+  if (G == 1) {
+    for (int e = threadIdx.x; e < nelem; e += SG_T) {
+      const cx<T> acc = element(e, 0);
+      out[e] = add ? add[e] + acc : acc;
+    }
+    sg_finish<T>(out, add, part, 1, nelem, false, 0, mk((T)0, (T)0));
+    return;
+  }
+  const int q = threadIdx.x / nelem, e = threadIdx.x - q * nelem;
+  const bool mine = q < G;
+  const cx<T> acc = mine ? element(e, q) : mk((T)0, (T)0);
+  sg_finish<T>(out, add, part, G, nelem, mine, e, acc);
+}
+
+// out = M x per site (M: nsite column-major nc x nc blocks)
+template <typename T>
+__device__ void sg_block_matvec(cx<T>* out, const cx<T>* M, const cx<T>* x, int nsite, int nc, cx<T>* part,
+                                cx<T>* xl) {
+  const size_t nn = (size_t)nc * nc;
+  const int nelem = nsite * nc;
+  for (int e = threadIdx.x; e < nelem; e += SG_T) xl[e] = x[e];
+  __syncthreads();
+  const int G = sg_groups(nelem, 8);
+  auto element = [&](int e, int q) {
+    const int ls = e / nc, row = e - ls * nc;
+    const cx<T>* Mk = M + (size_t)ls * nn + row;
+    const cx<T>* xk = xl + (size_t)ls * nc;
+    cx<T> sum = mk((T)0, (T)0);
+#pragma unroll 4
+    for (int k = q; k < nc; k += G) sum = sum + Mk[(size_t)k * nc] * xk[k];
+    return sum;
+  };
+  if (G == 1) {
+    for (int e = threadIdx.x; e < nelem; e += SG_T) out[e] = element(e, 0);
+    sg_finish<T>(out, nullptr, part, 1, nelem, false, 0, mk((T)0, (T)0));
+    return;
+  }
+  const int q = threadIdx.x / nelem, e = threadIdx.x - q * nelem;
+  const bool mine = q < G;
+  const cx<T> acc = mine ? element(e, q) : mk((T)0, (T)0);
+  sg_finish<T>(out, nullptr, part, G, nelem, mine, e, acc);
+}
+
+constexpr int SG_DB = 4;  // dot products per pass over w
+
+// h[j] = V_j^H w, j < nv (V_j = V + j vsj), summed in FP64; h in shared memory
+template <typename T>
+__device__ void sg_dots(cx<double>* h, const cx<T>* V, size_t vsj, int nv, const cx<T>* w, int n,
+                        cx<double> (*red)[SG_T / 64]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < nv; j0 += SG_DB) {
+    cx<double> acc[SG_DB];
+#pragma unroll
+    for (int q = 0; q < SG_DB; ++q) acc[q] = mk(0.0, 0.0);
+    for (int e = threadIdx.x; e < n; e += SG_T) {
+      const cx<double> wv = cvt<double>(w[e]);
+#pragma unroll
+      for (int q = 0; q < SG_DB; ++q)
+        if (j0 + q < nv) acc[q] = acc[q] + cmulc(cvt<double>(V[(size_t)(j0 + q) * vsj + e]), wv);
+    }
+#pragma unroll
+    for (int q = 0; q < SG_DB; ++q) {
+      const double re = wave_sum_d(acc[q].r), im = wave_sum_d(acc[q].i);
+      if (lane == 0) red[q][wid] = mk(re, im);
+    }
+    __syncthreads();
+    if (threadIdx.x < SG_DB && j0 + threadIdx.x < nv) {
+      cx<double> sum = mk(0.0, 0.0);
+      for (int k = 0; k < SG_T / 64; ++k) sum = sum + red[threadIdx.x][k];
+      h[j0 + threadIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// w[e] = f * (w[e] - sum_{j < nv} h[j] V_j[e])
+template <typename T>
+__device__ void sg_update(cx<T>* w, const cx<T>* V, size_t vsj, int nv, const cx<double>* h, double f, int n) {
+  for (int e = threadIdx.x; e < n; e += SG_T) {
+    cx<T> acc = w[e];
+    for (int j = 0; j < nv; ++j) acc = acc + cvt<T>(-1.0 * h[j]) * V[(size_t)j * vsj + e];
+    w[e] = cvt<T>(f * cvt<double>(acc));
+  }
+  __syncthreads();
+}
+
+template <typename T, typename S>
+__device__ void sg_schur(cx<T>* w, const cx<T>* v, cx<T>* te, cx<T>* ue, const CoarseView<S>& cv,
+                         const cx<T>* Dinv, int nc, int neven, int nodd, cx<T>* part, cx<T>* xl) {
+  const int nb = neven + nodd;
+  sg_stencil<T, S>(te, 0, neven, nullptr, nullptr, 0, (T)0, v, neven, (T)1, cv, nc, nb, part, xl);
+  sg_block_matvec<T>(ue, Dinv, te, neven, nc, part, xl);
+  sg_stencil<T, S>(w, neven, nodd, nullptr, v, neven, (T)1, ue, 0, (T)-1, cv, nc, nb, part, xl);
+}
+
+template <typename T, typename S>
+__global__ __launch_bounds__(SG_T) void coarse_gmres_small_kernel(cx<T>* xc, const cx<T>* yc, size_t cstr,
+                                                                  CoarseView<S> cv, const cx<T>* Dinv, int nc,
+                                                                  int neven, int nodd, cx<T>* te_, cx<T>* ue_,
+                                                                  cx<T>* bo_, cx<T>* cw_, cx<T>* V_, size_t vsj,
+                                                                  int m, int maxit, double tol, int* its_stat) {
+  __shared__ cx<double> red[SG_DB][SG_T / 64];
+  __shared__ cx<double> h1[SG_M + 1], h2[SG_M + 1];
+  // the Hessenberg matrix (column k at H + k (m + 1)), the rotations, the
+  // rotated rhs and the back-substituted coefficients: thread 0 updates
+  // them serially, so they live in LDS rather than behind global latency
+  __shared__ cx<double> H[(SG_M + 1) * SG_M], sn[SG_M], g[SG_M + 1], yv[SG_M];
+  __shared__ double cs[SG_M];
+  __shared__ cx<T> part[SG_T];
+  __shared__ cx<T> xl[COARSE_SMALL_MAX_VECTOR];
+  __shared__ int sh;
+  const int r = blockIdx.x;
+  const int nb = neven + nodd;
+  const int ne = neven * nc, no = nodd * nc;
+  const cx<T>* y = yc + (size_t)r * cstr;
+  cx<T>* x = xc + (size_t)r * cstr;
+  cx<T>* xo = x + ne;
+  cx<T>* te = te_ + (size_t)r * ne;
+  cx<T>* ue = ue_ + (size_t)r * ne;
+  cx<T>* bo = bo_ + (size_t)r * no;
+  cx<T>* cw = cw_ + (size_t)r * no;
+  cx<T>* V = V_ + (size_t)r * no;  // V_j = V + j vsj
+  // |y_c| -> absolute tolerance (tol < 0: never test)
+  sg_dots<T>(h1, y, 0, 1, y, ne + no, red);
+  const double abstol = tol < 0.0 ? -1.0 : tol * sqrt(fmax(h1[0].r, 0.0));
+  // b_o = y_o - D_oe D_ee^{-1} y_e, x_o = 0
+  sg_block_matvec<T>(te, Dinv, y, neven, nc, part, xl);
+  sg_stencil<T, S>(bo, neven, nodd, y + ne, nullptr, 0, (T)0, te, 0, (T)-1, cv, nc, nb, part, xl);
+  for (int e = threadIdx.x; e < no; e += SG_T) xo[e] = mk((T)0, (T)0);
+  __syncthreads();
+  int its = 0;
+  bool first = true;
+  while (its < maxit) {
+    // r = b_o - S x_o into V_0, its norm, the start of a cycle
+    if (first) {
+      for (int e = threadIdx.x; e < no; e += SG_T) V[e] = bo[e];
+      __syncthreads();
+    } else {
+      sg_schur<T, S>(cw, xo, te, ue, cv, Dinv, nc, neven, nodd, part, xl);
+      for (int e = threadIdx.x; e < no; e += SG_T) V[e] = bo[e] - cw[e];
+      __syncthreads();
+    }
+    first = false;
+    sg_dots<T>(h1, V, 0, 1, V, no, red);
+    const double beta = sqrt(fmax(h1[0].r, 0.0));
+    const bool act = abstol < 0.0 ? beta > 0.0 : beta > abstol;
+    if (!act) break;  // uniform: every lane computed beta from the same sums
+    if (threadIdx.x == 0) {
+      for (int j = 0; j <= m; ++j) g[j] = mk(0.0, 0.0);
+      g[0] = mk(beta, 0.0);
+    }
+    sg_update<T>(V, V, vsj, 0, h1, 1.0 / beta, no);
+    int k = 0;
+    for (; k < m && its < maxit; ++k) {
+      cx<T>* w = V + (size_t)(k + 1) * vsj;
+      sg_schur<T, S>(w, V + (size_t)k * vsj, te, ue, cv, Dinv, nc, neven, nodd, part, xl);
+      // classical Gram-Schmidt twice, then |w|^2
+      sg_dots<T>(h1, V, vsj, k + 1, w, no, red);
+      sg_update<T>(w, V, vsj, k + 1, h1, 1.0, no);
+      sg_dots<T>(h2, V, vsj, k + 1, w, no, red);
+      sg_update<T>(w, V, vsj, k + 1, h2, 1.0, no);
+      sg_dots<T>(h2 + k + 1, w, 0, 1, w, no, red);
+      int stop = 0;
+      double hn = 0.0;
+      if (threadIdx.x == 0) {
+        cx<double>* Hk = H + (size_t)k * (m + 1);
+        for (int j = 0; j <= k; ++j) Hk[j] = h1[j] + h2[j];
+        hn = sqrt(fmax(h2[k + 1].r, 0.0));
+        Hk[k + 1] = mk(hn, 0.0);
+        for (int j = 0; j < k; ++j) {
+          const double c = cs[j];
+          const cx<double> sj = sn[j];
+          const cx<double> t = c * Hk[j] + sj * Hk[j + 1];
+          Hk[j + 1] = c * Hk[j + 1] - conj(sj) * Hk[j];
+          Hk[j] = t;
+        }
+        double c;
+        cx<double> sv, rr;
+        givens(Hk[k], Hk[k + 1], c, sv, rr);
+        cs[k] = c;
+        sn[k] = sv;
+        Hk[k] = rr;
+        Hk[k + 1] = mk(0.0, 0.0);
+        const cx<double> gk = g[k];
+        g[k + 1] = neg(conj(sv) * gk);
+        g[k] = c * gk;
+        const double est = sqrt(cabs2(g[k + 1]));
+        stop = (!(hn > 0.0) || (abstol >= 0.0 && est <= abstol) || k + 1 >= m) ? 1 : 0;
+      }
+      stop = sg_flag(&sh, stop);
+      ++its;
+      if (stop) {
+        ++k;
+        break;
+      }
+      const double inv = 1.0 / sqrt(fmax(h2[k + 1].r, 0.0));
+      sg_update<T>(w, V, vsj, 0, h1, inv, no);
+    }
+    // y = H^{-1} g (upper triangular, k columns), then x_o += V y
+    if (threadIdx.x == 0) {
+      for (int i = k - 1; i >= 0; --i) {
+        cx<double> v = g[i];
+        for (int j = i + 1; j < k; ++j) v = v - H[(size_t)j * (m + 1) + i] * yv[j];
+        const cx<double> d = H[(size_t)i * (m + 1) + i];
+        const double dn = cabs2(d);
+        yv[i] = dn > 0.0 ? (1.0 / dn) * (conj(d) * v) : mk(0.0, 0.0);
+      }
+      for (int j = 0; j < k; ++j) h1[j] = neg(yv[j]);
+    }
+    __syncthreads();
+    sg_update<T>(xo, V, vsj, k, h1, 1.0, no);
+  }
+  // x_e = D_ee^{-1} (y_e - D_eo x_o)
+  sg_stencil<T, S>(te, 0, neven, y, nullptr, 0, (T)0, xo, neven, (T)-1, cv, nc, nb, part, xl);
+  sg_block_matvec<T>(x, Dinv, te, neven, nc, part, xl);
+  if (threadIdx.x == 0) {
+    atomicAdd(its_stat, its);
+    atomicMax(its_stat + 1, its);
+  }
+}
+
 // abstol[r] = tol * sqrt(|n2[r]|) (tol < 0: -1, i.e. never test)
 __global__ void set_abstol_kernel(double* abstol, const cx<double>* n2, double tol, int nrhs) {
   const int r = threadIdx.x;
@@ -350,6 +661,31 @@ __global__ void inv_norm_kernel(double* s, const cx<double>* n2, int nrhs, int* 
 }
 
 }  // namespace
+
+template <typename T, typename S>
+void launch_coarse_gmres_small(cx<T>* xc, const cx<T>* yc, size_t cstr, const CoarseView<S>& cv, const cx<T>* Dinv,
+                               const Geom& g, cx<T>* te, cx<T>* ue, cx<T>* bo, cx<T>* cw, cx<T>* V, size_t vsj,
+                               int m, int maxit, double tol, int* its_stat, int nrhs, hipStream_t st) {
+  if (nrhs <= 0) return;
+  if (m < 1 || m > SG_M || g.nblocks * g.nc > COARSE_SMALL_MAX_VECTOR)
+    throw std::runtime_error("single-kernel coarse solve: restart length or lattice above its bound");
+  coarse_gmres_small_kernel<T, S><<<nrhs, SG_T, 0, st>>>(xc, yc, cstr, cv, Dinv, g.nc, g.neven,
+                                                          g.nblocks - g.neven, te, ue, bo, cw, V, vsj, m, maxit, tol,
+                                                          its_stat);
+}
+template void launch_coarse_gmres_small<double, double>(cx<double>*, const cx<double>*, size_t,
+                                                        const CoarseView<double>&, const cx<double>*, const Geom&,
+                                                        cx<double>*, cx<double>*, cx<double>*, cx<double>*,
+                                                        cx<double>*, size_t, int, int, double, int*, int,
+                                                        hipStream_t);
+template void launch_coarse_gmres_small<float, float>(cx<float>*, const cx<float>*, size_t, const CoarseView<float>&,
+                                                      const cx<float>*, const Geom&, cx<float>*, cx<float>*,
+                                                      cx<float>*, cx<float>*, cx<float>*, size_t, int, int, double,
+                                                      int*, int, hipStream_t);
+template void launch_coarse_gmres_small<float, __half>(cx<float>*, const cx<float>*, size_t,
+                                                       const CoarseView<__half>&, const cx<float>*, const Geom&,
+                                                       cx<float>*, cx<float>*, cx<float>*, cx<float>*, cx<float>*,
+                                                       size_t, int, int, double, int*, int, hipStream_t);
 
 void launch_set_abstol(double* abstol, const cx<double>* n2, double tol, int nrhs, hipStream_t st) {
   set_abstol_kernel<<<1, 64, 0, st>>>(abstol, n2, tol, nrhs);

@@ -598,6 +598,9 @@ def test_coarse_pipelined_convergence_test(prec, restart):
     L, block, eps, m0, ntv = CASES["ragged_6x4x4x4"]
     say("coarse convergence test prec", prec, "restart", restart)
     ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, coarse_tol=1e-4, coarse_restart=restart)
+    # both variants of the multi-launch solve (this coarse lattice is small
+    # enough for the single-kernel one, which the host-sync switch turns off)
+    ctx.set_coarse_single_kernel(False)
     blk, W = _basis(L, block, ntv)
     ctx.import_basis(dev(W))
     y = dev(synth.gaussian_spinors(L, 3, 47))

@@ -305,7 +305,7 @@ namespace {
 
 // Krylov workspace of one GMRES instance (coarse or outer)
 struct Krylov {
-  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, any, kdone, h1, h2, n2, part, wscale;
+  DevBuf H, cs, sn, g, y, est, inv_h, abstol, active, any, kdone, h1, h2, hc, n2, part, wscale, vscale;
   int m = 0, maxr = 0, ldh = 0;
   size_t part_cap = 0;  // entries of part
   ArnoldiState st{};
@@ -326,8 +326,10 @@ struct Krylov {
     kdone.alloc<int>(maxr);
     h1.alloc<cx<double>>((size_t)maxr * ldh);
     h2.alloc<cx<double>>((size_t)maxr * ldh);
+    hc.alloc<cx<double>>((size_t)maxr * ldh);
     n2.alloc<cx<double>>(maxr);
     wscale.alloc<double>(maxr);
+    vscale.alloc<double>(maxr);
     part_cap = krylov_part_entries(m, maxr, n_per_rhs);
     part.alloc<cx<double>>(part_cap);
     st.H = H.get<cx<double>>();
@@ -847,31 +849,50 @@ struct Solver final : SolverBase {
 
   // ------------------------------------------------------- outer FGMRES
   // Classical Gram-Schmidt done twice against the outer basis V_0..V_k:
-  // h1 = V^H w; w <- w - V h1 and h2 = V^H w in one fused pass; the norm of
-  // w'' = w - V h2 from |w|^2 - |h2|^2 (V orthonormal); w <- w'' / |w''| in
-  // one pass.  The Arnoldi column is h1 + h2 with subdiagonal |w''|.
-  // w32: FP32 copy of the new basis vector (the next V-cycle's input), if given
+  // h1 = V^H w; w' = w - V h1 and h2 = V^H w' in one fused pass; |w''|^2 =
+  // |w'|^2 - |h2|^2 (V orthonormal).  The Arnoldi column is h1 + h2 with
+  // subdiagonal |w''|, complete after these two passes.  The vector itself,
+  // v_{k+1} = (w' - V h2) / |w''|, is formed in the next step's fused pass,
+  // which reads V_0..V_k anyway (gs_pending: slot k + 1 holds w', h2 and the
+  // factor wait in hc and wscale); the inner products of the next w with it
+  // follow from those with w' (launch_gs_defer_coef).  The preconditioner
+  // then receives w' (in FP32 its copy, scaled to about unit norm by an
+  // estimate of 1 / |w'| from the first pass, so that no FP32 quantity of
+  // the V-cycle underflows), which FGMRES allows: it needs D z_k in the span
+  // of V with the coefficients it records, whatever z_k is.  A step after which the next could not take the correction (basis
+  // longer than GS_FUSED_MAXV) writes v_{k+1} in a third pass as before.
+  bool gs_pending = false;
   void cgs2(cx<double>* V, size_t vsj, int k, int nrhs, cx<float>* w32) {
     const size_t n = fsz();
     const int* act = ok.active.get<int>();
     cx<double>* w = V + (size_t)(k + 1) * vsj;
     cx<double>* part = ok.part.get<cx<double>>();
-    need_part(launch_mdot<double>(ok.h1.get<cx<double>>(), ok.ldh, part, ok.part_cap, V, vsj, n, k + 1, w, n, n, nrhs,
-                                  act, st),
-              "outer Gram-Schmidt");
+    cx<double>* h1 = ok.h1.get<cx<double>>();
+    cx<double>* h2 = ok.h2.get<cx<double>>();
     if (k + 1 <= GS_FUSED_MAXV) {
-      need_part(launch_gs_fused(ok.h2.get<cx<double>>(), ok.ldh, part, ok.part_cap, V, vsj, n, k + 1, w, n,
-                                ok.h1.get<cx<double>>(), n, nrhs, act, st),
+      // h1 = V^H w and, as the inner product of the last vector (w itself),
+      // |w|^2, which gives the scale of the preconditioner's input
+      need_part(launch_mdot<double>(h1, ok.ldh, part, ok.part_cap, V, vsj, n, k + 2, w, n, n, nrhs, act, st),
                 "outer Gram-Schmidt");
+      launch_gs_defer_coef(h1, ok.hc.get<cx<double>>(), h2, ok.ldh, ok.wscale.get<double>(), k, gs_pending,
+                           ok.vscale.get<double>(), nrhs, act, st);
+      const bool defer = k + 2 <= GS_FUSED_MAXV;
+      need_part(launch_gs_defer(h2, ok.ldh, part, ok.part_cap, V, vsj, n, k, gs_pending, ok.hc.get<cx<double>>(),
+                                ok.wscale.get<double>(), w, n, h1, n, nrhs, act, defer ? w32 : nullptr,
+                                ok.vscale.get<double>(), st),
+                "outer Gram-Schmidt");
+      launch_gs_norm(ok.n2.get<cx<double>>(), ok.wscale.get<double>(), h2, ok.ldh, k + 1, nrhs, act, st);
+      gs_pending = defer;
+      if (defer) return;
     } else {  // long cycles: the same step in two passes (the last vector is w itself: |w|^2)
-      launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h1.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st);
-      need_part(launch_mdot<double>(ok.h2.get<cx<double>>(), ok.ldh, part, ok.part_cap, V, vsj, n, k + 2, w, n, n,
-                                    nrhs, act, st),
+      need_part(launch_mdot<double>(h1, ok.ldh, part, ok.part_cap, V, vsj, n, k + 1, w, n, n, nrhs, act, st),
                 "outer Gram-Schmidt");
+      launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, h1, ok.ldh, -1.0, n, nrhs, act, st);
+      need_part(launch_mdot<double>(h2, ok.ldh, part, ok.part_cap, V, vsj, n, k + 2, w, n, n, nrhs, act, st),
+                "outer Gram-Schmidt");
+      launch_gs_norm(ok.n2.get<cx<double>>(), ok.wscale.get<double>(), h2, ok.ldh, k + 1, nrhs, act, st);
     }
-    launch_gs_norm(ok.n2.get<cx<double>>(), ok.wscale.get<double>(), ok.h2.get<cx<double>>(), ok.ldh, k + 1, nrhs,
-                   act, st);
-    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, ok.h2.get<cx<double>>(), ok.ldh, -1.0, n, nrhs, act, st,
+    launch_maxpy<double, double>(w, n, V, vsj, n, k + 1, h2, ok.ldh, -1.0, n, nrhs, act, st,
                                  ok.wscale.get<double>(), w32);
   }
 
@@ -974,12 +995,13 @@ struct Solver final : SolverBase {
       }
       if (its >= c->p.outer_maxit) break;
       launch_arnoldi_start(ok.st, ok.n2.get<cx<double>>(), 1, nrhs, st);
-      // V-cycle input: in FP32 a copy written with each new basis vector, in
-      // FP64 the basis vector itself
+      // V-cycle input: in FP32 a copy written with each new basis vector (or
+      // with the w' that stands for it, see cgs2), in FP64 slot k itself
       constexpr bool f32 = std::is_same<T, float>::value;
       cx<float>* v32 = nullptr;
       if constexpr (f32) v32 = fy.get<cx<float>>();
       launch_scale<double, double>(V, n, V, n, ok.inv_h.get<double>(), n, nrhs, nullptr, st, v32);
+      gs_pending = false;
       int k = 0;
       for (; k < m && its < c->p.outer_maxit; ++k) {
         grow_outer(k + 2);
@@ -987,7 +1009,7 @@ struct Solver final : SolverBase {
         Z = oZ.get<cx<T>>();
         cx<double>* vk = V + (size_t)k * vsj;
         cx<T>* zk = Z + (size_t)k * vsj;
-        // z_k = M^{-1} v_k
+        // z_k = M^{-1} v_k (or M^{-1} w' while v_k is pending)
         if constexpr (f32)
           vcycle(zk, fy.get<cx<T>>(), nrhs);
         else

@@ -376,6 +376,19 @@ constexpr int GS_FUSED_MAXV = 24;
 bool launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap, const cx<double>* Vb,
                      size_t vstride_j, size_t vstride_r, int nvec, cx<double>* w, size_t wstride_r,
                      const cx<double>* h1, size_t n, int nrhs, const int* active, hipStream_t st);
+// The same pass with the previous step's second subtraction folded in: slot
+// k of Vb holds the pending vector u, replaced by v_k = sigma (u - sum_{j<k}
+// c_j V_j) if correct; then w <- w - sum_{j<=k} h_j V_j, w32 = FP32(wsc[r] w)
+// if given, h2[r][j] = V_j^H w (j <= k) and h2[r][k + 1] = |w|^2; k + 1 <= GS_FUSED_MAXV
+bool launch_gs_defer(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap, cx<double>* Vb, size_t vsj,
+                     size_t vsr, int k, bool correct, const cx<double>* c, const double* sigma, cx<double>* w,
+                     size_t wsr, const cx<double>* h, size_t n, int nrhs, const int* active, cx<float>* w32,
+                     const double* wsc, hipStream_t st);
+// With h[r][k + 1] = |w|^2: if correct, c[r][j] = h2[r][j] (j < k) and h[r][k] =
+// sigma[r] (h[r][k] - sum_{j<k} conj(c_j) h[r][j]); then wsc[r] = 1 / |w - sum_{j<=k}
+// h_j V_j| estimated from |w|^2 - sum |h_j|^2 (nrhs <= 64)
+void launch_gs_defer_coef(cx<double>* h, cx<double>* c, const cx<double>* h2, int ldh, const double* sigma, int k,
+                          bool correct, double* wsc, int nrhs, const int* active, hipStream_t st);
 // n2[r] = h2[r][nvec] - sum_{j<nvec} |h2[r][j]|^2, inv[r] = 1/sqrt(n2[r]) (0 if not positive)
 void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs,
                     const int* active, hipStream_t st);

@@ -162,6 +162,120 @@ __global__ __launch_bounds__(BT) void gs_fused_kernel(cx<double>* part, const cx
   }
 }
 
+// Second step of classical Gram-Schmidt done twice with the subtraction of
+// the previous step's second projection deferred into it.  Slot k holds the
+// pending vector u (the previous new vector, projected once); with the
+// previous second-projection coefficients c and normalisation sigma it
+// becomes v_k = sigma (u - sum_{j<k} c_j V_j), the vector a separate pass
+// would have written, and is stored back (correct = false: u is v_k
+// already).  In the same pass over the data: w <- w - sum_{j<=k} h_j V_j
+// with the corrected v_k, its FP32 copy in w32 if given, and the partial
+// sums of V_j^H w (j <= k) and |w|^2 as gs_fused_kernel writes them.
+// The FP32 copy is scaled by wsc[r] (an estimate of 1 / |w''|) so that the
+// preconditioner, which receives it, sees a vector of about unit norm.
+template <int MAXV>
+__global__ __launch_bounds__(BT) void gs_defer_kernel(cx<double>* part, cx<double>* Vb, size_t vsj, size_t vsr, int k,
+                                                      int correct, const cx<double>* __restrict__ c, int ldc,
+                                                      const double* __restrict__ sigma, cx<double>* w, size_t wsr,
+                                                      const cx<double>* __restrict__ h, int ldh, size_t n,
+                                                      size_t chunk, int nchunk, const int* active, cx<double>* h2,
+                                                      cx<float>* w32, const double* __restrict__ wsc) {
+  __shared__ cx<double> red[MAXV + 1][BT / 64];
+  const int cb = blockIdx.x;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int nvec = k + 1;
+  const size_t beg = (size_t)cb * chunk;
+  const size_t end = min(n, beg + chunk);
+  cx<double>* wr = w + (size_t)r * wsr;
+  cx<double>* uk = Vb + (size_t)k * vsj + (size_t)r * vsr;
+  const cx<double>* hr = h + (size_t)r * ldh;
+  const cx<double>* cr = c + (size_t)r * ldc;
+  const double sg = sigma[r];
+  const double ws = w32 ? wsc[r] : 1.0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  cx<double> acc[MAXV];
+  double nacc = 0.0;
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) acc[j] = mk(0.0, 0.0);
+  for (size_t i = beg + threadIdx.x; i < end; i += BT) {
+    cx<double> v[MAXV];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < k) v[j] = Vb[(size_t)j * vsj + (size_t)r * vsr + i];
+    cx<double> u = uk[i];
+    if (correct) {
+#pragma unroll
+      for (int j = 0; j < MAXV; ++j)
+        if (j < k) u = u - cr[j] * v[j];
+      u = sg * u;
+      uk[i] = u;
+    }
+    cx<double> x = wr[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nvec) {
+        if (j == k) v[j] = u;
+        x = x - hr[j] * v[j];
+      }
+    wr[i] = x;
+    if (w32) w32[(size_t)r * wsr + i] = cvt<float>(ws * x);
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nvec) acc[j] = acc[j] + cmulc(v[j], x);
+    nacc += x.r * x.r + x.i * x.i;
+  }
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    if (j < nvec) {
+      const double re = wave_sum_d(acc[j].r), im = wave_sum_d(acc[j].i);
+      if (lane == 0) red[j][wid] = mk(re, im);
+    }
+  }
+  nacc = wave_sum_d(nacc);
+  if (lane == 0) red[nvec][wid] = mk(nacc, 0.0);
+  __syncthreads();
+  for (int j = threadIdx.x; j <= nvec; j += BT) {
+    cx<double> sum = mk(0.0, 0.0);
+    for (int q = 0; q < BT / 64; ++q) sum = sum + red[j][q];
+    if (nchunk == 1)
+      h2[(size_t)r * ldh + j] = sum;
+    else
+      part[((size_t)r * (nvec + 1) + j) * nchunk + cb] = sum;
+  }
+}
+
+// Before the deferred pass, with h[r][0..k] = V_j^H w and h[r][k + 1] =
+// |w|^2 from the first pass: if correct, c[r][j] = h2[r][j] (j < k), the
+// pending vector's corrections, kept apart from h2 (which that pass
+// overwrites), and h[r][k] = sigma_r (h[r][k] - sum_{j<k} conj(c_j) h[r][j]),
+// the inner product of w with the corrected v_k from those with the stored
+// vectors; then wsc[r] = 1 / |w'| from |w'|^2 = |w|^2 - sum_{j<=k} |h_j|^2,
+// floored at 1e-20 |w|^2 against cancellation (only a scale: the exact
+// |w''| follows the pass).
+__global__ void gs_defer_coef_kernel(cx<double>* h, cx<double>* c, const cx<double>* h2, int ldh,
+                                     const double* sigma, int k, int correct, double* wsc, int nrhs,
+                                     const int* active) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  if (active && !active[r]) return;
+  cx<double>* hr = h + (size_t)r * ldh;
+  if (correct) {
+    cx<double> d = hr[k];
+    for (int j = 0; j < k; ++j) {
+      const cx<double> cj = h2[(size_t)r * ldh + j];
+      c[(size_t)r * ldh + j] = cj;
+      d = d - conj(cj) * hr[j];
+    }
+    hr[k] = sigma[r] * d;
+  }
+  const double w2 = hr[k + 1].r;
+  double e = w2;
+  for (int j = 0; j <= k; ++j) e -= hr[j].r * hr[j].r + hr[j].i * hr[j].i;
+  e = fmax(e, 1e-20 * w2);
+  wsc[r] = (e > 0.0 && isfinite(e)) ? 1.0 / sqrt(e) : 0.0;
+}
+
 // |w''|^2 = |w'|^2 - sum_j |h2_j|^2 (w'' = w' - V h2 with V orthonormal),
 // and the factor that normalises w''; zero for a vanishing or non-finite
 // norm (the Arnoldi step then stops that rhs)
@@ -737,6 +851,39 @@ bool launch_gs_fused(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap,
                                                         active, h2);
   if (nchunk > 1) mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
   return true;
+}
+
+bool launch_gs_defer(cx<double>* h2, int ldh, cx<double>* part, size_t part_cap, cx<double>* Vb, size_t vsj,
+                     size_t vsr, int k, bool correct, const cx<double>* c, const double* sigma, cx<double>* w,
+                     size_t wsr, const cx<double>* h, size_t n, int nrhs, const int* active, cx<float>* w32,
+                     const double* wsc, hipStream_t st) {
+  if (nrhs <= 0) return true;
+  const int nvec = k + 1;
+  if (nvec > GS_FUSED_MAXV || mdot_part_entries(n, nvec + 1, nrhs) > part_cap) return false;
+  const int nchunk = blas_nchunks(n);
+  const size_t chunk = (n + nchunk - 1) / nchunk;
+  dim3 grid(nchunk, nrhs);
+  const int cr = correct ? 1 : 0;
+  if (nvec <= 4)
+    gs_defer_kernel<4><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, k, cr, c, ldh, sigma, w, wsr, h, ldh, n, chunk, nchunk,
+                                            active, h2, w32, wsc);
+  else if (nvec <= 8)
+    gs_defer_kernel<8><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, k, cr, c, ldh, sigma, w, wsr, h, ldh, n, chunk, nchunk,
+                                            active, h2, w32, wsc);
+  else if (nvec <= 16)
+    gs_defer_kernel<16><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, k, cr, c, ldh, sigma, w, wsr, h, ldh, n, chunk,
+                                             nchunk, active, h2, w32, wsc);
+  else
+    gs_defer_kernel<GS_FUSED_MAXV><<<grid, BT, 0, st>>>(part, Vb, vsj, vsr, k, cr, c, ldh, sigma, w, wsr, h, ldh, n,
+                                                        chunk, nchunk, active, h2, w32, wsc);
+  if (nchunk > 1)
+    mdot_final_kernel<<<dim3(nvec + 1, nrhs), 64, 0, st>>>(h2, ldh, part, nvec + 1, nchunk, active);
+  return true;
+}
+
+void launch_gs_defer_coef(cx<double>* h, cx<double>* c, const cx<double>* h2, int ldh, const double* sigma, int k,
+                          bool correct, double* wsc, int nrhs, const int* active, hipStream_t st) {
+  gs_defer_coef_kernel<<<1, 64, 0, st>>>(h, c, h2, ldh, sigma, k, correct ? 1 : 0, wsc, nrhs, active);
 }
 
 void launch_gs_norm(cx<double>* n2, double* inv, const cx<double>* h2, int ldh, int nvec, int nrhs, const int* active,

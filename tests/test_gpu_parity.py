@@ -263,6 +263,47 @@ def test_solve_residual(case, prec):
         assert rel(uh[0], uo) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_solve_long_outer_cycle(prec):
+    """A deliberately weak preconditioner (N_tv 2, one SAP cycle of one MR
+    step, no setup passes, one coarse iteration; the oracle needs 52 outer
+    iterations on this field) with FGMRES(30): the first cycle runs all 30
+    iterations, through the two-pass Gram-Schmidt with the deferred
+    subtraction (k <= 22), the step that completes the last pending vector
+    (k = 23) and the three-pass steps of a long basis (k >= 24), then
+    restarts.  Both rhs reach 1e-10, recomputed by the oracle's FP64 D; in
+    FP64 the oracle's own solve of the first rhs takes the same number of
+    outer iterations (within one) and gives the same solution (1e-12;
+    6e-16 measured)."""
+    dd = _gpu()
+    L, block, m0, ntv = (8, 8, 8, 8), (4, 4, 4, 4), -0.2, 2
+    say("long outer cycle prec", prec)
+    ctx, U = make_ctx(dd, L, block, 0.5, m0, ntv, prec, gauge_seed=61, max_rhs=2, n_setup=0, nu=1, n_mr=1,
+                      coarse_fixed_its=1, outer_restart=30)
+    ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 62)))
+    A = dirac.clover_term(U, m0, 1.0)
+    f = synth.gaussian_spinors(L, 2, 63)
+    u = torch.zeros_like(dev(f))
+    rc, st = ctx.solve(u, dev(f), 2, 1e-10)
+    say("  outer iterations %d, restarts %d, relres %s" % (st["outer_iterations"], st["outer_restarts"],
+                                                           st["relres"][:2]))
+    assert rc == 0, st
+    assert st["outer_iterations"] > 30 and st["outer_restarts"] >= 1
+    uh = host(u)
+    for r in range(2):
+        res = f[r] - dirac.apply_D(U, A, uh[r])
+        assert np.linalg.norm(res) / np.linalg.norm(f[r]) <= 1e-10
+    ctx.close()
+    if prec == 0:
+        p = mg.Params(L, block, m0, 1.0, ntv, n_setup=0, nu=1, n_mr=1, coarse_fixed_its=1, outer_restart=30)
+        M = mg.MG(p, U)
+        M.setup(synth.gaussian_spinors(L, ntv, 62))
+        uo, sto = M.solve(f[0])
+        say("  oracle: %d outer iterations, solution rel diff %.2e" % (sto["iterations"], rel(uh[0], uo)))
+        assert abs(sto["iterations"] - st["outer_iterations"]) <= 1
+        assert rel(uh[0], uo) <= 1e-12
+
+
 def test_solve_batching_invariance():
     """rhs k solved alone equals rhs k solved in a batch (independent Krylov
     per rhs, shared launches), up to the solver tolerance."""

@@ -115,6 +115,15 @@ def test_import_rejects_null_and_missing_setup(dd):
     assert dd.lib.ddamg_import_coarse(None, None) == -1
 
 
+def test_switches_reject_null_context(dd):
+    """The per-context switches return the argument error for a NULL context
+    before touching anything (no GPU needed)."""
+    for name in ("ddamg_set_coarse_host_sync", "ddamg_set_graphs", "ddamg_set_coarse_single_kernel",
+                 "ddamg_set_kernel_timing"):
+        for on in (0, 1):
+            assert getattr(dd.lib, name)(None, on) == -1, name
+
+
 def test_params_struct_matches_the_header(dd, tmp_path):
     """The ctypes mirror of ddamg_params has the C struct's size and field
     offsets (a C program compiled against the header prints them), and the

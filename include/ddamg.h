@@ -286,11 +286,13 @@ int ddamg_set_coarse_host_sync(ddamg_ctx* ctx, int each_iteration);
  * Many small lattices of uneven sizes, each its own context, served
  * together: a pool of `workers` host threads (1 <= workers <= 64) takes the
  * instances in array order, each thread running one instance's call at a
- * time, so the kernels of up to `workers` instances are in flight at once.
+ * time, so the kernels of up to `workers` instances are in flight at once;
+ * an instance whose stream already has another instance in flight waits
+ * and the next one is taken.
  * A small lattice fills a few compute units per launch; the instances'
  * kernels overlap on the GPU only if their contexts were created on
- * different streams (contexts sharing a stream are still served correctly,
- * one after the other on that stream).  Each instance gets exactly the
+ * different streams (contexts sharing a stream, as ones drawn from a stream
+ * pool may, are served one after the other, never concurrently).  Each instance gets exactly the
  * result of the single-instance call (same kernels, same order of work).
  * ctx[0 .. n-1] must be distinct contexts (a context is not thread-safe).
  * Per instance: rc[i] its return code; begin_ms[i] and end_ms[i] (either
@@ -310,9 +312,10 @@ int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const doub
  * iteration's launches (the Schur-complement stencil, the Gram-Schmidt
  * passes, the Arnoldi column, the scaling) are captured once per iteration
  * index and rhs count into a HIP graph on the context's stream and
- * replayed, one launch call per iteration instead of ten: what bounds the
- * solve of a small lattice is the host's launch rate.  Results are
- * identical either way.  Contexts on the null stream, and any context while
+ * replayed, one launch call per iteration instead of ten.  (Measured on
+ * small lattices this changes little: the chain of small dependent kernels
+ * on the device, not the host's launch calls, bounds such a solve.)
+ * Results are identical either way.  Contexts on the null stream, and any context while
  * kernel timing is on, launch eagerly.  on = 0 launches eagerly always. */
 int ddamg_set_graphs(ddamg_ctx* ctx, int on);
 

@@ -11,11 +11,13 @@
 #include <atomic>
 #include <map>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <thread>
 #include <unordered_set>
@@ -53,6 +55,34 @@ inline void need_part(bool launched, const char* what) {
   if (!launched) throw Fail{DDAMG_ENOMEM, std::string(what) + ": partial-sum workspace too small"};
 }
 
+// Graph capture against device-wide calls.  HIP refuses a free or a device
+// synchronisation while a stream of the process is being captured (the
+// refused call's error then surfaces at a later check of that thread), and
+// contexts served from several host threads capture on their own streams
+// while other threads set up or grow their buffers.  So every capture holds
+// this gate shared (captures on different streams still overlap) and every
+// allocation, free or synchronous copy of the library holds it exclusively.
+// An allocation inside a capture would deadlock on it and is refused.
+std::shared_mutex g_capture_gate;
+thread_local bool t_capturing = false;
+using GateExclusive = std::unique_lock<std::shared_mutex>;
+
+void* pinned_alloc(size_t bytes) {
+  if (t_capturing) throw Fail{DDAMG_EHIP, "host allocation inside a graph capture"};
+  GateExclusive lk(g_capture_gate);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{DDAMG_ENOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  return p;
+}
+void pinned_free(void* p) {
+  if (!p) return;
+  GateExclusive lk(g_capture_gate);
+  (void)hipHostFree(p);
+}
+
 // Workspace allocator: hipMalloc / hipFree unless the caller installed a
 // hook; every buffer remembers the release function it was allocated with.
 ddamg_alloc_fn g_alloc = nullptr;
@@ -73,7 +103,9 @@ struct DevBuf {
   }
   template <typename X>
   X* alloc(size_t n) {
-    release();
+    if (t_capturing) throw Fail{DDAMG_EHIP, "device allocation inside a graph capture"};
+    GateExclusive lk(g_capture_gate);
+    release_locked();
     const size_t bytes = (n == 0 ? 1 : n) * sizeof(X);
     if (g_alloc) {
       p = g_alloc(bytes, g_alloc_user);
@@ -93,6 +125,11 @@ struct DevBuf {
     return get<X>();
   }
   void release() {
+    if (!p) return;
+    GateExclusive lk(g_capture_gate);
+    release_locked();
+  }
+  void release_locked() {
     if (p) {
       if (fr) {
         // hipFree waits for the device; a hook need not, so wait here (rare:
@@ -263,14 +300,14 @@ struct ddamg_ctx {
     return r;
   }
   void free_pinned() {
-    if (h_flags) (void)hipHostFree(h_flags);
-    if (h_ring) (void)hipHostFree(h_ring);
+    pinned_free(h_flags);
+    pinned_free(h_ring);
     for (auto& e : ring_ev)
       if (e) (void)hipEventDestroy(e);
     h_ring = nullptr;
     ring_ev[0] = ring_ev[1] = nullptr;
-    if (h_dbl) (void)hipHostFree(h_dbl);
-    if (h_cx) (void)hipHostFree(h_cx);
+    pinned_free(h_dbl);
+    pinned_free(h_cx);
     h_flags = nullptr;
     h_dbl = nullptr;
     h_cx = nullptr;
@@ -420,10 +457,17 @@ struct Solver final : SolverBase {
     }
     auto it = step_graphs.find({k, nrhs});
     if (it == step_graphs.end()) {
-      // thread-local capture: other contexts may capture on other threads
+      // thread-local capture: other contexts may capture on other threads;
+      // the gate keeps other threads' allocations and frees out of it
+      std::shared_lock<std::shared_mutex> gate(g_capture_gate);
+      struct Flag {
+        Flag() { t_capturing = true; }
+        ~Flag() { t_capturing = false; }
+      } flag;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         use_graphs = false;  // a stream that cannot be captured: stay eager
+        t_capturing = false;
         enqueue();
         return;
       }
@@ -450,6 +494,7 @@ struct Solver final : SolverBase {
     its = coarse_its_total;
     itmax = coarse_its_max;
     int dev[2] = {0, 0};
+    GateExclusive lk(g_capture_gate);
     if (hipStreamSynchronize(st) == hipSuccess &&
         hipMemcpy(dev, small_its.get<int>(), sizeof(dev), hipMemcpyDeviceToHost) == hipSuccess) {
       its += dev[0];
@@ -1145,6 +1190,7 @@ void build_tables(ddamg_ctx* c) {
       }
   }
   c->nbr.alloc<int>(nbr.size());
+  GateExclusive lk(g_capture_gate);
   HIPCK(hipMemcpy(c->nbr.get<int>(), nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
 }
 
@@ -1259,8 +1305,8 @@ struct ddamg_net {
   }
 
   ~ddamg_net() {
-    if (h_loss) (void)hipHostFree(h_loss);
-    if (h_stat) (void)hipHostFree(h_stat);
+    pinned_free(h_loss);
+    pinned_free(h_stat);
   }
 };
 
@@ -1272,20 +1318,50 @@ namespace {
 // caller) serve every instance.  rc[i] and the times are written by the
 // thread that ran instance i.
 template <typename F>
-int serve_batch(int n, int workers, int32_t* rc, double* begin_ms, double* end_ms, F&& one) {
-  std::atomic<int> next{0};
+int serve_batch(ddamg_ctx* const* ctx, int n, int workers, const std::vector<int>& order, int32_t* rc,
+                double* begin_ms, double* end_ms, F&& one) {
+  // Each worker takes the first instance in `order` whose stream has no
+  // other instance in flight: contexts may share a stream (a stream pool
+  // hands out a limited number), and two calls on one stream from two
+  // threads would interleave their work, or put one's launches into the
+  // other's graph capture.  Such instances run one after the other.
+  std::mutex mx;
+  std::condition_variable freed;
+  std::vector<char> taken(n, 0);
+  std::vector<hipStream_t> busy;
+  int head = 0, left = n;
   const auto start = std::chrono::steady_clock::now();
   auto ms = [&] { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - start).count(); };
   auto work = [&] {
     for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= n) return;
+      int i = -1;
+      {
+        std::unique_lock<std::mutex> lk(mx);
+        for (;;) {
+          if (left == 0) return;
+          for (int q = head; q < n && i < 0; ++q) {
+            const int j = order[q];
+            if (!taken[j] && std::find(busy.begin(), busy.end(), ctx[j]->st) == busy.end()) i = j;
+          }
+          if (i >= 0) break;
+          freed.wait(lk);
+        }
+        taken[i] = 1;
+        --left;
+        busy.push_back(ctx[i]->st);
+        while (head < n && taken[order[head]]) ++head;
+      }
       const double a = ms();
       const int r = one(i);
       const double b = ms();
       rc[i] = r;
       if (begin_ms) begin_ms[i] = a;
       if (end_ms) end_ms[i] = b;
+      {
+        std::lock_guard<std::mutex> lk(mx);
+        busy.erase(std::find(busy.begin(), busy.end(), ctx[i]->st));
+      }
+      freed.notify_all();
     }
   };
   std::vector<std::thread> pool;
@@ -1304,6 +1380,12 @@ int serve_batch(int n, int workers, int32_t* rc, double* begin_ms, double* end_m
     if (rc[i] == DDAMG_NOT_CONVERGED) any_nc = 1;
   }
   return first_neg ? first_neg : (any_nc ? DDAMG_NOT_CONVERGED : DDAMG_OK);
+}
+
+std::vector<int> array_order(int n) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  return order;
 }
 
 int check_batch(ddamg_ctx* const* ctx, int n, int workers, const int32_t* rc) {
@@ -1391,11 +1473,11 @@ int ddamg_create(const ddamg_params* p, const double* gauge, void* stream, ddamg
     g.lstr[0] = 1;
     for (int mu = 1; mu < 4; ++mu) g.lstr[mu] = g.lstr[mu - 1] * g.bs[mu - 1];
     build_tables(c.get());
-    HIPCK(hipHostMalloc((void**)&c->h_flags, 64 * sizeof(int), hipHostMallocDefault));
-    HIPCK(hipHostMalloc((void**)&c->h_ring, 2 * 64 * sizeof(int), hipHostMallocDefault));
+    c->h_flags = static_cast<int*>(pinned_alloc(64 * sizeof(int)));
+    c->h_ring = static_cast<int*>(pinned_alloc(2 * 64 * sizeof(int)));
     for (auto& e : c->ring_ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIPCK(hipHostMalloc((void**)&c->h_dbl, 128 * sizeof(double), hipHostMallocDefault));
-    HIPCK(hipHostMalloc((void**)&c->h_cx, 128 * sizeof(cx<double>), hipHostMallocDefault));
+    c->h_dbl = static_cast<double*>(pinned_alloc(128 * sizeof(double)));
+    c->h_cx = static_cast<cx<double>*>(pinned_alloc(128 * sizeof(cx<double>)));
     c->status.alloc<int>(1);
     const size_t V = g.V;
     c->U64.alloc<cx<double>>(36 * V);
@@ -1818,7 +1900,8 @@ int ddamg_set_coarse_single_kernel(ddamg_ctx* c, int on) {
 
 int ddamg_batch_setup(ddamg_ctx* const* ctx, int n, int workers, int32_t* rc, double* begin_ms, double* end_ms) {
   if (int e = check_batch(ctx, n, workers, rc)) return e;
-  return serve_batch(n, workers, rc, begin_ms, end_ms, [&](int i) { return mg_setup(ctx[i], nullptr); });
+  return serve_batch(ctx, n, workers, array_order(n), rc, begin_ms, end_ms,
+                     [&](int i) { return mg_setup(ctx[i], nullptr); });
 }
 
 int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const double* const* f, const int32_t* nrhs,
@@ -1839,7 +1922,7 @@ int ddamg_batch_solve(ddamg_ctx* const* ctx, int n, double* const* u, const doub
     }
     if (int e = need_setup(c)) return e;
   }
-  return serve_batch(n, workers, rc, begin_ms, end_ms,
+  return serve_batch(ctx, n, workers, array_order(n), rc, begin_ms, end_ms,
                      [&](int i) { return solve(ctx[i], u[i], f[i], nrhs[i], tol, nullptr); });
 }
 
@@ -1902,8 +1985,8 @@ int ddamg_net_create(const int32_t* channels, int32_t nlayers, void* stream, dda
     HIPCK(hipMemsetAsync(n->W.p, 0, sizeof(cx<float>) * n->nw, n->st));
     HIPCK(hipMemsetAsync(n->m.p, 0, sizeof(cx<float>) * n->nw, n->st));
     HIPCK(hipMemsetAsync(n->v.p, 0, sizeof(cx<float>) * n->nw, n->st));
-    HIPCK(hipHostMalloc((void**)&n->h_loss, sizeof(double), hipHostMallocDefault));
-    HIPCK(hipHostMalloc((void**)&n->h_stat, sizeof(int), hipHostMallocDefault));
+    n->h_loss = static_cast<double*>(pinned_alloc(sizeof(double)));
+    n->h_stat = static_cast<int*>(pinned_alloc(sizeof(int)));
     n->sync();
   } catch (const Fail& f) {
     g_create_error = f.msg;

@@ -131,6 +131,62 @@ def test_batch_timings_are_consistent(batch):
         assert np.all(b >= 0) and np.all(e >= b)
 
 
+def test_batch_serves_in_array_order(batch):
+    """One worker starts the instances in array order; the solutions are bit
+    for bit those of the batch above."""
+    dd, insts, U, f, ctxs, ub, info, sinfo = batch
+    fd = [dev(x) for x in f]
+    ud = [torch.zeros_like(x) for x in fd]
+    torch.cuda.synchronize()
+    rc, out = dd.batch_solve(ctxs, ud, fd, 1, TOL, workers=1)
+    assert rc == 0
+    got = [int(i) for i in np.argsort(np.array(out["begin_ms"]), kind="stable")]
+    assert got == list(range(len(insts)))
+    for k in range(len(insts)):
+        assert np.array_equal(host(ud[k]), ub[k])
+
+
+def test_batch_concurrent_capture_and_allocation():
+    """Fresh contexts served by 8 workers: while some instances capture
+    their coarse iterations into graphs, others allocate and free their
+    setup and Krylov buffers on other threads (HIP refuses a free during any
+    capture of the process; the library keeps the two apart), and the 16
+    contexts share 6 streams, as contexts drawn from a stream pool do: the
+    pool never runs two instances of one stream at once (their calls do not
+    overlap in time), and every instance's setup and solve succeed."""
+    dd = _gpu()
+    by = {}
+    for inst in synth.uneven_instances(64, 23):
+        by.setdefault(inst["L"], []).append(inst)
+    insts = [i for L in synth.UNEVEN_SHAPES for i in by[L][:4]]
+    U = [synth.su3_field(i["L"], i["eps"], i["gauge_seed"]) for i in insts]
+    streams = [torch.cuda.Stream() for _ in range(6)]
+    ctxs = []
+    for k, (inst, u) in enumerate(zip(insts, U)):
+        p = dd.default_params(L=inst["L"], block=inst["block"], m0=inst["m0"], csw=inst["csw"], ntv=inst["ntv"],
+                              prec=dd.FP32, max_rhs=1, seed=inst["setup_seed"])
+        Ud = dev(u)
+        torch.cuda.synchronize()
+        ctxs.append(dd.Context(p, Ud, stream=streams[k % 6]))
+    torch.cuda.synchronize()
+    say("concurrent capture: %d fresh contexts, 8 workers" % len(ctxs))
+    rc, info = dd.batch_setup(ctxs, workers=8)
+    assert rc == 0, info["rc"]
+    fd = [dev(synth.gaussian_spinors(i["L"], 1, i["rhs_seed"])) for i in insts]
+    ud = [torch.zeros_like(x) for x in fd]
+    torch.cuda.synchronize()
+    rc, sinfo = dd.batch_solve(ctxs, ud, fd, 1, TOL, workers=8)
+    say("  setup rc %s, solve rc %s" % (info["rc"], sinfo["rc"]))
+    assert rc == 0, sinfo["rc"]
+    for d in (info, sinfo):
+        for s0 in range(6):
+            iv = sorted((d["begin_ms"][k], d["end_ms"][k]) for k in range(len(ctxs)) if k % 6 == s0)
+            assert all(iv[q][1] <= iv[q + 1][0] for q in range(len(iv) - 1)), iv
+    for c in ctxs:
+        assert max(c.stats()["relres"][:1]) <= TOL
+        c.close()
+
+
 def test_batch_argument_errors(batch):
     dd, insts, U, f, ctxs, ub, info, sinfo = batch
     fd = [dev(x) for x in f[:2]]

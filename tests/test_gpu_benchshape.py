@@ -16,7 +16,7 @@ tests run exactly those shapes on the smallest lattice that holds them,
 and the 16^4 workload (4^4 blocks, N_tv 20, FP32 preconditioner, 8
 Gaussian rhs) through setup and solve, every residual recomputed by the
 oracle's D.  Tolerances are relative to the largest element of the oracle's
-output: the benchmark spec's 1e-12 / 1e-5 / 1e-2 (FP64 / FP32 / FP16 storage) for
+output: 1e-12 / 1e-5 / 1e-2 (FP64 / FP32 / FP16 storage, the parity bars) for
 the operator applies and the V-cycle, 1e-11 / 1e-5 / 1e-2 for the setup.
 """
 import sys
@@ -36,11 +36,11 @@ BLOCK = (4, 4, 4, 4)
 EPS, M0, CSW, NTV = 0.5, -0.2, 1.0, 24
 FIXED_ITS, COARSE_RESTART = 6, 4  # a restart inside the fixed coarse iterations
 NRHS_MAX = 24
-# operator applies (the benchmark spec): FP64 1e-12, FP32 1e-5, 16-bit storage 1e-2
+# operator applies (the parity bars): FP64 1e-12, FP32 1e-5, 16-bit storage 1e-2
 TOL_OP = {0: 1e-12, 1: 1e-5, 2: 1e-2}
 # composites: V-cycle and setup chain dozens of applies and inner products;
 # measured here 8e-16 / 3.4e-7 / 3.0e-4 (V-cycle) and 1.1e-15 / 3.1e-7 /
-# 8.3e-4 (setup basis), so the benchmark spec's bars hold for them as well
+# 8.3e-4 (setup basis), so the same bars hold for them as well
 TOL_VCYCLE = {0: 1e-12, 1: 1e-5, 2: 1e-2}
 TOL_SETUP = {0: 1e-11, 1: 1e-5, 2: 1e-2}
 

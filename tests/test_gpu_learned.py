@@ -2,7 +2,7 @@
 ABI) against the oracle: the network's forward pass, the span loss and the
 gradient of every weight, one Adam step, and a short training run whose loss
 falls.  FP32 arithmetic on the device: tolerance 1e-5 relative to the
-largest element (the benchmark spec's FP32 bar) for the proposal and the loss, and
+largest element (the FP32 parity bar) for the proposal and the loss, and
 for the gradients of every layer.
 
 Network 3 -> 5 -> 6 -> 4 channels (three layers, two gates; 5 and 6 leave

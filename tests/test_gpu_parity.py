@@ -304,6 +304,41 @@ def test_solve_long_outer_cycle(prec):
         assert rel(uh[0], uo) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("kind", ["free_field", "no_clover"])
+def test_degenerate_operator(kind, prec):
+    """Degenerate cases of the operator: the free field (every link the
+    identity) and c_sw = 0 (the clover term is the mass term alone).  D
+    applies within the parity bar of its precision, and the solve reaches
+    1e-10, recomputed by the oracle's FP64 D."""
+    dd = _gpu()
+    L, block, ntv, m0 = (4, 4, 4, 4), (2, 2, 2, 2), 8, -0.1
+    if kind == "free_field":
+        U, csw = np.broadcast_to(np.eye(3, dtype=np.complex128), tuple(reversed(L)) + (4, 3, 3)).copy(), 1.0
+    else:
+        U, csw = synth.su3_field(L, 0.4, 7), 0.0
+    say("degenerate operator", kind, "prec", prec)
+    p = dd.default_params(L=L, block=block, m0=m0, csw=csw, ntv=ntv, prec=prec, max_rhs=ntv)
+    ctx = dd.Context(p, dev(U))
+    A = dirac.clover_term(U, m0, csw)
+    psi = synth.gaussian_spinors(L, 2, 11)
+    out = torch.zeros_like(dev(psi))
+    ctx.dirac_apply(out, dev(psi), 2, prec)
+    ref = np.stack([dirac.apply_D(U, A, psi[r]) for r in range(2)])
+    assert rel(host(out), ref) <= TOL[prec]
+    ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 102)))
+    f = synth.gaussian_spinors(L, 2, 103)
+    u = torch.zeros_like(dev(f))
+    rc, st = ctx.solve(u, dev(f), 2, 1e-10)
+    say("  outer iterations %d" % st["outer_iterations"])
+    assert rc == 0, st
+    uh = host(u)
+    for r in range(2):
+        res = f[r] - dirac.apply_D(U, A, uh[r])
+        assert np.linalg.norm(res) / np.linalg.norm(f[r]) <= 1e-10
+    ctx.close()
+
+
 def test_solve_batching_invariance():
     """rhs k solved alone equals rhs k solved in a batch (independent Krylov
     per rhs, shared launches), up to the solver tolerance."""

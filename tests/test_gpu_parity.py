@@ -339,6 +339,37 @@ def test_degenerate_operator(kind, prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_maximum_rhs_count(prec):
+    """64 right-hand sides, the largest max_rhs: two 32-rhs tiles of the
+    matrix-core restriction, four 16-rhs tiles of the coarse stencil, every
+    lane of the 64-thread Arnoldi kernels.  D applies within the parity bar,
+    and all 64 solutions reach 1e-10, recomputed by the oracle's FP64 D."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    n = 64
+    say("maximum rhs count prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, max_rhs=n)
+    A = dirac.clover_term(U, m0, 1.0)
+    psi = synth.gaussian_spinors(L, n, 11)
+    out = torch.zeros_like(dev(psi))
+    ctx.dirac_apply(out, dev(psi), n, prec)
+    ref = np.stack([dirac.apply_D(U, A, psi[r]) for r in range(n)])
+    assert rel(host(out), ref) <= TOL[prec]
+    ctx.mg_setup(dev(synth.gaussian_spinors(L, ntv, 102)))
+    f = synth.gaussian_spinors(L, n, 103)
+    u = torch.zeros_like(dev(f))
+    rc, st = ctx.solve(u, dev(f), n, 1e-10)
+    say("  outer iterations %d" % st["outer_iterations"])
+    assert rc == 0, st
+    uh = host(u)
+    for r in range(n):
+        res = f[r] - dirac.apply_D(U, A, uh[r])
+        assert np.linalg.norm(res) / np.linalg.norm(f[r]) <= 1e-10
+        assert st["relres"][r] <= 1e-10
+    ctx.close()
+
+
 def test_solve_batching_invariance():
     """rhs k solved alone equals rhs k solved in a batch (independent Krylov
     per rhs, shared launches), up to the solver tolerance."""

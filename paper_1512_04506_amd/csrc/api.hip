@@ -437,6 +437,7 @@ struct Solver final : SolverBase {
   // iteration); its iteration counts accumulate on the device
   bool use_small_coarse = true;
   DevBuf small_its;  // [2] iterations summed, maximum
+  DevBuf u_nonzero;  // [maxr] flags: the solve's initial guess has a nonzero entry
   ~Solver() override {
     for (auto& kv : step_graphs) (void)hipGraphExecDestroy(kv.second);
   }
@@ -541,6 +542,7 @@ struct Solver final : SolverBase {
     npart.alloc<cx<double>>(npart_cap);
     small_its.alloc<int>(2);
     HIPCK(hipMemsetAsync(small_its.get<int>(), 0, 2 * sizeof(int), st));
+    u_nonzero.alloc<int>(maxr);
   }
 
   // ------------------------------------------------------------ smoother
@@ -988,15 +990,23 @@ struct Solver final : SolverBase {
     cx<double>* u = ou.get<cx<double>>();
     const GaugeView<double> g64 = c->gv64();
     launch_spinor_to_internal<double>(f, reinterpret_cast<const cx<double>*>(f_canon), g, nrhs, st);
-    launch_spinor_to_internal<double>(u, reinterpret_cast<const cx<double>*>(u_canon), g, nrhs, st);
+    // the conversion of u also flags the rhs whose initial guess is nonzero
+    HIPCK(hipMemsetAsync(u_nonzero.get<int>(), 0, sizeof(int) * nrhs, st));
+    launch_spinor_to_internal<double>(u, reinterpret_cast<const cx<double>*>(u_canon), g, nrhs, st,
+                                      u_nonzero.get<int>());
     // ||f||
     need_part(launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), ok.part_cap, f, 0, n, 1, f, n,
                                   n, nrhs, nullptr, st),
               "right-hand side norm");
     std::vector<cx<double>> fn2(nrhs), rn2(nrhs);
     HIPCK(hipMemcpyAsync(c->h_cx, ok.n2.get<cx<double>>(), sizeof(cx<double>) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(c->h_flags, u_nonzero.get<int>(), sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
     c->sync();
     std::copy(c->h_cx, c->h_cx + nrhs, fn2.begin());
+    // all initial guesses zero: the first residual is f itself (D 0 = 0
+    // exactly), a copy instead of the FP64 operator and a subtraction
+    bool u_zero = true;
+    for (int r = 0; r < nrhs; ++r) u_zero = u_zero && c->h_flags[r] == 0;
     std::vector<double> fnorm(nrhs), abstol(nrhs), zero_scale(nrhs, 1.0);
     bool any_zero = false;
     for (int r = 0; r < nrhs; ++r) {
@@ -1018,9 +1028,13 @@ struct Solver final : SolverBase {
     std::vector<double> relres(nrhs, 0.0);
     for (;;) {
       // true residual r = f - D u in FP64, into V_0
-      c->timed(DDAMG_KERNEL_RESIDUAL, nrhs,
-               [&] { launch_dslash<double, double, double, double>(w, u, g64, g, nrhs, DS_FULL, 0, -1, n, n, st); });
-      launch_sub<double>(V, n, f, n, w, n, n, nrhs, st);
+      if (u_zero && its == 0) {
+        launch_copy<double, double>(V, n, f, n, n, nrhs, st);
+      } else {
+        c->timed(DDAMG_KERNEL_RESIDUAL, nrhs,
+                 [&] { launch_dslash<double, double, double, double>(w, u, g64, g, nrhs, DS_FULL, 0, -1, n, n, st); });
+        launch_sub<double>(V, n, f, n, w, n, n, nrhs, st);
+      }
       need_part(launch_mdot<double>(ok.n2.get<cx<double>>(), 1, ok.part.get<cx<double>>(), ok.part_cap, V, 0, n, 1, V,
                                     n, n, nrhs, nullptr, st),
                 "residual norm");

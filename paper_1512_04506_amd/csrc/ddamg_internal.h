@@ -249,7 +249,10 @@ template <typename S>
 void launch_quantize_gauge(stc_t<S>* Uq, float* Usc, stc_t<S>* Aq, float* Asc, const cx<double>* U,
                            const cx<double>* A, const Geom& g, hipStream_t st);
 template <typename T>
-void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st);
+// nonzero (if given, nrhs ints the caller zeroed): nonzero[r] = 1 when the
+// canonical field of rhs r has a nonzero entry
+void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st,
+                               int* nonzero = nullptr);
 template <typename T>
 void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st);
 void launch_clover_export(cx<double>* out, const cx<double>* A, const Geom& g, hipStream_t st);

@@ -186,20 +186,40 @@ __global__ void quantize_gauge_kernel(stc_t<S>* Uq, float* Usc, stc_t<S>* Aq, fl
 // are one contiguous 192-byte record, the internal components are 12
 // site-contiguous planes, so both sides are read/written in full lines.
 template <typename T>
-__global__ void spinor_to_internal_kernel(cx<T>* out, const cx<double>* canon, Geom g, int nrhs) {
+__global__ void spinor_to_internal_kernel(cx<T>* out, const cx<double>* canon, Geom g, int nrhs, int* nonzero) {
   const size_t V = g.V;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)nrhs * V) return;
-  const int s = (int)(idx % V);
-  const size_t r = idx / V;
-  int c[4];
-  site_coords(g, s, c);
-  const cx<double>* src = canon + (r * V + lex_site(g, c)) * 12;
-  cx<double> v[12];
+  const bool valid = idx < (size_t)nrhs * V;
+  const size_t ic = valid ? idx : 0;
+  const int s = (int)(ic % V);
+  const size_t r = ic / V;
+  bool nz = false;
+  if (valid) {
+    int c[4];
+    site_coords(g, s, c);
+    const cx<double>* src = canon + (r * V + lex_site(g, c)) * 12;
+    cx<double> v[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) v[k] = src[k];
+    for (int k = 0; k < 12; ++k) v[k] = src[k];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) out[(r * 12 + k) * V + s] = cvt<T>(v[k]);
+    for (int k = 0; k < 12; ++k) {
+      out[(r * 12 + k) * V + s] = cvt<T>(v[k]);
+      nz = nz || v[k].r != 0.0 || v[k].i != 0.0;
+    }
+  }
+  if (nonzero) {
+    // nonzero[r] = 1 if the field of rhs r has a nonzero entry: one atomic
+    // per wave and rhs present in it (the loop is uniform over the wave)
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(valid && nz);
+    while (todo) {
+      const int l0 = __ffsll((unsigned long long)todo) - 1;
+      const size_t rl = (size_t)__shfl((long long)r, l0, 64);
+      const unsigned long long mine = __ballot(valid && nz && r == rl);
+      if (lane == l0) atomicOr(&nonzero[rl], 1);
+      todo &= ~mine;
+    }
+  }
 }
 
 template <typename T>
@@ -320,17 +340,18 @@ template void launch_quantize_gauge<__half>(stc_t<__half>*, float*, stc_t<__half
                                             const cx<double>*, const Geom&, hipStream_t);
 
 template <typename T>
-void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st) {
+void launch_spinor_to_internal(cx<T>* out, const cx<double>* canon, const Geom& g, int nrhs, hipStream_t st,
+                               int* nonzero) {
   size_t n = (size_t)nrhs * 12 * g.V;
-  if (n) spinor_to_internal_kernel<T><<<nblk(n / 12), TPB, 0, st>>>(out, canon, g, nrhs);
+  if (n) spinor_to_internal_kernel<T><<<nblk(n / 12), TPB, 0, st>>>(out, canon, g, nrhs, nonzero);
 }
 template <typename T>
 void launch_spinor_to_canonical(cx<double>* canon, const cx<T>* in, const Geom& g, int nrhs, hipStream_t st) {
   size_t n = (size_t)nrhs * 12 * g.V;
   if (n) spinor_to_canonical_kernel<T><<<nblk(n / 12), TPB, 0, st>>>(canon, in, g, nrhs);
 }
-template void launch_spinor_to_internal<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
-template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, const Geom&, int, hipStream_t);
+template void launch_spinor_to_internal<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t, int*);
+template void launch_spinor_to_internal<float>(cx<float>*, const cx<double>*, const Geom&, int, hipStream_t, int*);
 template void launch_spinor_to_canonical<double>(cx<double>*, const cx<double>*, const Geom&, int, hipStream_t);
 template void launch_spinor_to_canonical<float>(cx<double>*, const cx<float>*, const Geom&, int, hipStream_t);
 

@@ -370,6 +370,45 @@ def test_maximum_rhs_count(prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [0, 2])
+def test_solve_initial_guess(prec):
+    """The solve starts from the caller's u.  All three cases reach 1e-10
+    (recomputed by the oracle's D): every guess zero (the first residual is f,
+    no operator applied), every guess nonzero (the oracle's solution plus a
+    perturbation: the first residual is f - D u), and a mix of both in one
+    call; a guess equal to the oracle's solution needs at most one cycle."""
+    dd = _gpu()
+    L, block, eps, m0, ntv = CASES["c1_4x4x4x4"]
+    say("initial guess prec", prec)
+    ctx, U = make_ctx(dd, L, block, eps, m0, ntv, prec, max_rhs=ntv)
+    tv = synth.gaussian_spinors(L, ntv, 102)
+    ctx.mg_setup(dev(tv))
+    A = dirac.clover_term(U, m0, 1.0)
+    f = synth.gaussian_spinors(L, 3, 103)
+    p = mg.Params(L, block, m0, 1.0, ntv)
+    M = mg.MG(p, U)
+    M.setup(tv)
+    uo = np.stack([M.solve(f[r])[0] for r in range(3)])
+    noise = synth.gaussian_spinors(L, 3, 104)
+    guesses = {"zero": np.zeros_like(f), "near": uo + 1e-3 * noise,
+               "mixed": np.stack([np.zeros_like(f[0]), uo[1] + 1e-3 * noise[1], noise[2]])}
+    its = {}
+    for name, g0 in guesses.items():
+        u = dev(g0.copy())
+        rc, st = ctx.solve(u, dev(f), 3, 1e-10)
+        assert rc == 0, (name, st)
+        uh = host(u)
+        for r in range(3):
+            res = f[r] - dirac.apply_D(U, A, uh[r])
+            assert np.linalg.norm(res) / np.linalg.norm(f[r]) <= 1e-10, (name, r)
+        its[name] = st["outer_iterations"]
+    say("  outer iterations %s" % its)
+    u = dev(uo.copy())
+    rc, st = ctx.solve(u, dev(f), 3, 1e-10)
+    assert rc == 0 and st["outer_iterations"] <= ctx.params.outer_restart
+    ctx.close()
+
+
 def test_solve_batching_invariance():
     """rhs k solved alone equals rhs k solved in a batch (independent Krylov
     per rhs, shared launches), up to the solver tolerance."""

@@ -208,7 +208,7 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=float), q))
 
 
-def batched_serving(dd, torch, n=64, seed=401, workers=(1, 2, 4, 8, 16), field_workers=16):
+def batched_serving(dd, torch, n=64, seed=401, workers=(1, 2, 4, 8, 16), field_workers=16, setup_workers=8):
     """Batched serving of uneven instances: n independent lattices of the
     uneven-instance recipe (8^4, 8^3 x 16, 12^4 with 2^4 blocks, 16^4; N_tv
     16; FP32 preconditioner, FP64 outer; one Gaussian rhs each), every
@@ -236,7 +236,7 @@ def batched_serving(dd, torch, n=64, seed=401, workers=(1, 2, 4, 8, 16), field_w
     del U
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, sinfo = dd.batch_setup(ctxs, workers=8)
+    rc, sinfo = dd.batch_setup(ctxs, workers=setup_workers)
     setup_ms = (time.perf_counter() - t0) * 1e3
     if rc != 0:
         raise RuntimeError("batched setup: rc %d %s" % (rc, sinfo["rc"]))
@@ -273,7 +273,8 @@ def batched_serving(dd, torch, n=64, seed=401, workers=(1, 2, 4, 8, 16), field_w
         k = "x".join(str(x) for x in i["L"])
         shapes[k] = shapes.get(k, 0) + 1
     return {"instances": n, "seed": seed, "shapes": shapes, "ntv": 16, "prec": "FP32 preconditioner, FP64 outer",
-            "nrhs_per_instance": 1, "tol": 1e-10, "input_generation_s": gen_s, "setup_makespan_ms_8_workers": setup_ms,
+            "nrhs_per_instance": 1, "tol": 1e-10, "input_generation_s": gen_s, "setup_workers": setup_workers,
+            "setup_makespan_ms": setup_ms,
             "outer_iterations_min_max": [min(its), max(its)], "relres_max": relres,
             "by_workers": {str(k): v for k, v in runs.items()}, "best_workers": best,
             "speedup_best_vs_1_worker": runs[best]["solves_per_s"] / runs[1]["solves_per_s"] if 1 in runs else None}
@@ -634,6 +635,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coarse-cost", action="store_true")
+    ap.add_argument("--batched-only", type=int, default=0, metavar="WORKERS",
+                    help="serve only the 64 uneven instances with this many workers and print their JSON (for "
+                         "profiling the small-instance path); no step is timed")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched serving of 64 uneven instances")
     ap.add_argument("--learned", action="store_true",
@@ -655,6 +659,10 @@ def main():
     log("workload", w["name"])
     if args.learned:
         print(json.dumps({"learned_setup": learned_eval(dd, torch, w, args)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_uneven": batched_serving(dd, torch, workers=(args.batched_only,),
+                                                            setup_workers=args.batched_only)}), flush=True)
         return
     t = time.perf_counter()
     U, tv, f = make_inputs(w)

@@ -5,10 +5,11 @@
              solution.
   setup   -- Alg. 4 with Alg. 5: random test vectors (passed in), three
              smoother passes with N_smoother = 1, 2, 3 from a zero guess,
-             aggregate Gram-Schmidt and D_c, normalisation, then N_setup
-             passes that replace every test vector by the V-cycle applied to
-             it (R and D_c frozen during a pass), renormalise, and rebuild
-             R and D_c.
+             aggregate Gram-Schmidt and D_c, one normalisation of the test
+             vectors, then N_setup passes that replace every test vector by
+             the V-cycle applied to it (R and D_c frozen during a pass) and
+             rebuild R and D_c (the algorithm normalises only once, after
+             the initial setup).
   fgmres  -- right-preconditioned flexible GMRES(m) for D u = f (Sec. 1:
              solve D M^{-1} v = f, u = M^{-1} v), modified Gram-Schmidt,
              Givens rotations, stopped on |g_{j+1}| <= tol ||f||, with the
@@ -103,7 +104,6 @@ class MG:
         V = _normalise(V)
         for _ in range(self.p.n_setup):
             V = np.stack([self.vcycle(V[j]) for j in range(len(V))])
-            V = _normalise(V)
             self.build_coarse(V)
         self.V = V
         return V

@@ -812,12 +812,14 @@ struct Solver final : SolverBase {
     }
     build_coarse();
     normalise(V, n);
-    // iterative setup: every test vector replaced by the V-cycle applied to it
+    // iterative setup: every test vector replaced by the V-cycle applied to
+    // it, then R and D_c rebuilt (Alg. 4 normalises once, above; the
+    // V-cycle is homogeneous and the aggregate Gram-Schmidt invariant to the
+    // length of a vector, so the lengths only ride along)
     for (int i = 0; i < c->p.n_setup; ++i) {
       tv.swap(fy);
       V = tv.get<cx<T>>();
       vcycle(V, fy.get<cx<T>>(), n);
-      normalise(V, n);
       build_coarse();
     }
     c->sync();

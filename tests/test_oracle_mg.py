@@ -103,10 +103,12 @@ def test_setup_composition_with_decoupled_blocks():
     cut, D is block diagonal; with the block MR run to convergence every SAP
     cycle returns the block solve, so each smoother pass from zero and each
     V-cycle (whatever the coarse correction gave as start) returns D^{-1} y.
-    Alg. 4 then leaves every test vector along D^{-(3 + N_setup)} v for its
-    start vector v (three smoother passes, N_setup V-cycle passes), unit
-    normalised, and the basis is their aggregate Gram-Schmidt.  A pass too
-    many or too few changes the power and fails the check."""
+    Alg. 4 then leaves every test vector at D^{-N_setup} x3 with x3 =
+    D^{-3} v / |D^{-3} v| for its start vector v (three smoother passes, the
+    one normalisation after the initial setup, N_setup V-cycle passes), and
+    the basis is their aggregate Gram-Schmidt.  A pass too many or too few
+    changes the power, and a normalisation after the last pass changes the
+    length: either fails the check."""
     Ls, bs, ntv, n_setup = (4, 4, 2, 2), (2, 2, 1, 1), 4, 2
     U = synth.su3_field(Ls, 0.5, 61)
     c = dirac.coords(Ls)
@@ -120,12 +122,17 @@ def test_setup_composition_with_decoupled_blocks():
     D = dense_from_apply(M.D, shp)
     for j in range(ntv):
         x = v0[j].reshape(-1)
-        for _ in range(3 + n_setup):
+        for _ in range(3):
             x = np.linalg.solve(D, x)
         x /= np.linalg.norm(x)
+        for _ in range(n_setup):
+            x = np.linalg.solve(D, x)
         assert relerr(V[j].reshape(-1), x) < 1e-9
-        # one power fewer is far off (the check has teeth)
-        assert relerr(V[j].reshape(-1), D @ x / np.linalg.norm(D @ x)) > 1e-3
+        # one power fewer is far off, and so is the unit vector along x (the
+        # check has teeth for the passes and for where the normalisation is)
+        assert relerr(V[j].reshape(-1), D @ x) > 1e-3
+        assert abs(np.linalg.norm(x) - 1.0) > 1e-3
+        assert relerr(V[j].reshape(-1), x / np.linalg.norm(x)) > 1e-3
     assert relerr(M.W, coarse.orthonormalise(M.blk, V)) < 1e-12
 
 
